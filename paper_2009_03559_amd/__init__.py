@@ -1,0 +1,233 @@
+"""Python binding of libhfx (ctypes).  Argument marshalling only: every step of
+the exchange build runs in the HIP library.  PyTorch supplies device memory
+and streams.  There is no CPU fallback: if the built library is missing, every
+call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libhfx.so")
+
+HFX_OK, HFX_EINVAL, HFX_EUNSUPPORTED, HFX_ENOMEM, HFX_EBUSY, HFX_ENOTFOUND, HFX_EDEVICE, HFX_EASYM = range(8)
+STATUS_NAMES = ["OK", "EINVAL", "EUNSUPPORTED", "ENOMEM", "EBUSY", "ENOTFOUND", "EDEVICE", "EASYM"]
+OP_COULOMB, OP_ERFC = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+NCLASS = 21
+PAIR_CLASSES = ["ss", "ps", "pp", "ds", "dp", "dd"]
+CLASS_NAMES = [f"({PAIR_CLASSES[b]}|{PAIR_CLASSES[k]})" for b in range(6) for k in range(b + 1)]
+
+# Symbols declared in include/hfx.h.
+EXPORTS = ["hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_K_batch",
+           "hfx_server_create", "hfx_submit", "hfx_poll", "hfx_pairs_nbf", "hfx_pairs_npair",
+           "hfx_pairs_device_bytes", "hfx_eval_quartets", "hfx_pairs_destroy", "hfx_server_destroy",
+           "hfx_last_error"]
+
+
+class HfxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 8 else status}: {msg}")
+        self.status = status
+
+
+class Shell(ctypes.Structure):
+    _fields_ = [("atom", ctypes.c_int32), ("l", ctypes.c_int32), ("nprim", ctypes.c_int32),
+                ("prim_off", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("op", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("prec", ctypes.c_int32), ("mixed_cut", ctypes.c_double), ("prim_tau", ctypes.c_double),
+                ("flags", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("latency_s", ctypes.c_double), ("device_s", ctypes.c_double), ("quartets", ctypes.c_int64),
+                ("quartets_fp32", ctypes.c_int64), ("prim_quartets", ctypes.c_int64), ("flops", ctypes.c_double),
+                ("class_quartets", ctypes.c_int64 * NCLASS)]
+
+    def as_dict(self):
+        return dict(latency_s=self.latency_s, device_s=self.device_s, quartets=self.quartets,
+                    quartets_fp32=self.quartets_fp32, prim_quartets=self.prim_quartets, flops=self.flops,
+                    class_quartets=list(self.class_quartets))
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library (raises if it is missing: no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HfxError(HFX_EDEVICE, f"libhfx.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.hfx_last_error.restype = ctypes.c_char_p
+        L.hfx_build_shell_pairs.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, vp,
+                                            ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+        L.hfx_schwarz_bounds.argtypes = [vp, ctypes.POINTER(Opts), vp, vp]
+        L.hfx_build_K.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(Opts), vp, ctypes.POINTER(Stats)]
+        L.hfx_build_K_batch.argtypes = [ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp,
+                                        ctypes.POINTER(Stats)]
+        L.hfx_server_create.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(vp)]
+        L.hfx_submit.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_uint64)]
+        L.hfx_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Stats)]
+        L.hfx_eval_quartets.argtypes = [vp, ctypes.POINTER(Opts), ctypes.c_int64, vp, vp, vp]
+        for f in ("hfx_pairs_nbf", "hfx_pairs_npair", "hfx_pairs_device_bytes"):
+            getattr(L, f).argtypes = [vp]
+            getattr(L, f).restype = ctypes.c_int64
+        L.hfx_pairs_destroy.argtypes = [vp]
+        L.hfx_pairs_destroy.restype = None
+        L.hfx_server_destroy.argtypes = [vp]
+        L.hfx_server_destroy.restype = None
+        for f in ("hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_K_batch",
+                  "hfx_server_create", "hfx_submit", "hfx_poll", "hfx_eval_quartets"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != HFX_OK:
+        raise HfxError(rc, lib().hfx_last_error().decode())
+
+
+def opts(tau=1e-10, omega=0.0, prec=PREC_FP64, mixed_cut=1e-5, op=None) -> Opts:
+    if op is None:
+        op = OP_ERFC if omega > 0 else OP_COULOMB
+    return Opts(tau=float(tau), op=int(op), omega=float(omega), prec=int(prec), mixed_cut=float(mixed_cut),
+                prim_tau=0.0, flags=0)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(a):
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Pairs:
+    """Device-resident shell-pair data of one system (owns the handle)."""
+
+    def __init__(self, handle, nbf, nshell):
+        self.handle = handle
+        self.nbf = nbf
+        self.nshell = nshell
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().hfx_pairs_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    @property
+    def device_bytes(self):
+        return lib().hfx_pairs_device_bytes(self.handle)
+
+
+def build_shell_pairs(xyz, shell_atom, shell_l, shell_nprim, shell_off, exps, coefs, o=None, stream=None) -> Pairs:
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    n = len(shell_l)
+    sh = (Shell * n)()
+    for i in range(n):
+        sh[i] = Shell(int(shell_atom[i]), int(shell_l[i]), int(shell_nprim[i]), int(shell_off[i]))
+    ex = np.ascontiguousarray(exps, dtype=np.float64)
+    co = np.ascontiguousarray(coefs, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().hfx_build_shell_pairs(_ptr(xyz), int(xyz.shape[0]), ctypes.cast(sh, ctypes.c_void_p), n,
+                                       _ptr(ex), _ptr(co), ctypes.byref(o) if o is not None else None,
+                                       _stream_ptr(stream), ctypes.byref(h)))
+    return Pairs(h, int(lib().hfx_pairs_nbf(h)), n)
+
+
+def pairs_from_system(sys, o=None, stream=None) -> Pairs:
+    return build_shell_pairs(sys.xyz, sys.shell_atom, sys.shell_l, sys.shell_nprim, sys.shell_off, sys.exps,
+                             sys.coefs, o, stream)
+
+
+def schwarz_bounds(p: Pairs, o: Opts, stream=None) -> np.ndarray:
+    q = np.zeros(p.nshell * (p.nshell + 1) // 2, dtype=np.float64)
+    _check(lib().hfx_schwarz_bounds(p.handle, ctypes.byref(o), _ptr(q), _stream_ptr(stream)))
+    return q
+
+
+def build_K(p: Pairs, P, K, o: Opts, stream=None, stats=False):
+    """P, K: device tensors (n_bf x n_bf float64, row stride = ld)."""
+    ld = int(P.stride(0)) if hasattr(P, "stride") else p.nbf
+    if hasattr(K, "stride") and int(K.stride(0)) != ld:
+        raise HfxError(HFX_EINVAL, "P and K must share the leading dimension")
+    st = Stats() if stats else None
+    _check(lib().hfx_build_K(p.handle, _ptr(P), _ptr(K), ld, ctypes.byref(o), _stream_ptr(stream),
+                             ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def build_K_batch(pairs, Ps, Ks, o: Opts, stream=None, stats=False):
+    n = len(pairs)
+    hs = (ctypes.c_void_p * n)(*[p.handle.value if isinstance(p.handle, ctypes.c_void_p) else p.handle for p in pairs])
+    pp = (ctypes.c_void_p * n)(*[P.data_ptr() for P in Ps])
+    kp = (ctypes.c_void_p * n)(*[K.data_ptr() for K in Ks])
+    ld = (ctypes.c_int64 * n)(*[int(P.stride(0)) for P in Ps])
+    st = Stats() if stats else None
+    _check(lib().hfx_build_K_batch(n, ctypes.cast(hs, ctypes.c_void_p), ctypes.cast(pp, ctypes.c_void_p),
+                                   ctypes.cast(kp, ctypes.c_void_p), ctypes.cast(ld, ctypes.c_void_p),
+                                   ctypes.byref(o), _stream_ptr(stream),
+                                   ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def eval_quartets(p: Pairs, o: Opts, quartets, shell_l, stream=None):
+    """Raw spherical integrals of shell quartets (n, 4) -> list of arrays."""
+    q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
+    sizes = [int(np.prod([2 * shell_l[s] + 1 for s in row])) for row in q]
+    out = np.zeros(int(sum(sizes)), dtype=np.float64)
+    _check(lib().hfx_eval_quartets(p.handle, ctypes.byref(o), q.shape[0], _ptr(q), _ptr(out), _stream_ptr(stream)))
+    res, off = [], 0
+    for row, n in zip(q, sizes):
+        res.append(out[off:off + n].reshape([2 * shell_l[s] + 1 for s in row]))
+        off += n
+    return res
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4):
+        h = ctypes.c_void_p()
+        _check(lib().hfx_server_create(int(hbm_budget_bytes), int(max_inflight), ctypes.byref(h)))
+        self.handle = h
+
+    def submit(self, p: Pairs, P, K, o: Opts) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().hfx_submit(self.handle, p.handle, _ptr(P), _ptr(K), int(P.stride(0)), ctypes.byref(o),
+                                ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int32()
+        st = Stats()
+        _check(lib().hfx_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(st)))
+        return bool(done.value), (st.as_dict() if done.value else None)
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().hfx_server_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

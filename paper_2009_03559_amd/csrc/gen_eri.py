@@ -1,0 +1,455 @@
+#!/usr/bin/env python3
+"""Generate the per-class device code of the shell-quartet kernels.
+
+For every angular-momentum class (la lb | lc ld) with l <= 2, la >= lb,
+lc >= ld, this writes a struct with two straight-line device functions:
+
+  vrr   one primitive quartet: the Obara-Saika vertical recurrence from the
+        auxiliary integrals [00|00]^(m) to the targets [e0|f0]^(0) with
+        la <= |e| <= la+lb and lc <= |f| <= lc+ld, accumulated into the
+        contracted array (Head-Gordon-Pople order: vertical on primitives,
+        horizontal after contraction).  Only the nodes the targets depend on
+        are emitted; the decrement direction of every node is chosen so the
+        dependency graph stays small.
+  post  one contracted quartet: horizontal recurrence on the bra
+        (b+1_i from a+1_i and A-B), spherical transform of the bra, then the
+        same on the ket (C-D), giving (2la+1)(2lb+1)(2lc+1)(2ld+1) values.
+
+The ket vertical step is optionally split into groups of f components
+(`--split`): group g emits only the nodes its f targets need, so several lanes
+can share one quartet, each holding a slice of the contracted array.
+
+All index tables and coefficients are compile-time constants in the output,
+so the device compiler keeps every intermediate in registers.  The file also
+reports operation counts (an FMA counts two) used for the FLOP model.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+from functools import lru_cache
+
+LMAX = 2
+
+
+def cart(l):
+    """Cartesian monomials of degree l: x descending, then y descending."""
+    out = []
+    for i in range(l, -1, -1):
+        for j in range(l - i, -1, -1):
+            out.append((i, j, l - i - j))
+    return out
+
+
+def ncart(l):
+    return (l + 1) * (l + 2) // 2
+
+
+# Spherical rows on Cartesians normalised like x^l (p: x, y, z; d: m = -2..2).
+R3 = math.sqrt(3.0)
+SPH = {
+    0: [{(0, 0, 0): 1.0}],
+    1: [{(1, 0, 0): 1.0}, {(0, 1, 0): 1.0}, {(0, 0, 1): 1.0}],
+    2: [{(1, 1, 0): R3}, {(0, 1, 1): R3}, {(0, 0, 2): 1.0, (2, 0, 0): -0.5, (0, 2, 0): -0.5},
+        {(1, 0, 1): R3}, {(2, 0, 0): 0.5 * R3, (0, 2, 0): -0.5 * R3}],
+}
+
+
+def sub(t, i, k=1):
+    l = list(t)
+    l[i] -= k
+    return tuple(l)
+
+
+def add(t, i, k=1):
+    l = list(t)
+    l[i] += k
+    return tuple(l)
+
+
+def classes():
+    pcs = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+    out = []
+    for cb in range(6):
+        for ck in range(cb + 1):
+            out.append(pcs[cb] + pcs[ck])
+    return out
+
+
+def fmt(x):
+    r = repr(float(x))
+    return r if ("." in r or "e" in r) else r + ".0"
+
+
+class Emitter:
+    def __init__(self, T="double"):
+        self.lines = []
+        self.flops = 0
+        self.T = T
+
+    def lit(self, x):
+        s = fmt(x)
+        return s + "f" if self.T == "float" else s
+
+
+# ------------------------------------------------------------------ VRR ----
+def vrr_graph(la, lb, lc, ld, f_targets=None, policy="auto"):
+    """Needed nodes (e, f, m) and each node's recurrence (direction, preds)."""
+    E, F = la + lb, lc + ld
+    L = E + F
+    e_t = [e for d in range(la, E + 1) for e in cart(d)]
+    f_all = [f for d in range(lc, F + 1) for f in cart(d)]
+    f_t = f_all if f_targets is None else f_targets
+    best = None
+    policies = ["first", "small", "large", "last"] if policy == "auto" else [policy]
+    for pol in policies:
+        rec = {}
+
+        def pick(t):
+            nz = [i for i in range(3) if t[i] > 0]
+            if pol == "first":
+                return nz[0]
+            if pol == "last":
+                return nz[-1]
+            if pol == "small":
+                return min(nz, key=lambda i: (t[i], i))
+            return max(nz, key=lambda i: (t[i], -i))
+
+        order = []
+        seen = set()
+
+        def need(node):
+            if node in seen:
+                return
+            e, f, m = node
+            if sum(e) == 0 and sum(f) == 0:
+                seen.add(node)
+                rec[node] = ("base",)
+                order.append(node)
+                return
+            if sum(f) > 0:
+                i = pick(f)
+                f1 = sub(f, i)
+                preds = [("QC", i, (e, f1, m)), ("WQ", i, (e, f1, m + 1))]
+                if f1[i] > 0:
+                    f2 = sub(f1, i)
+                    preds.append(("F2", i, f1[i], (e, f2, m), (e, f2, m + 1)))
+                if e[i] > 0:
+                    preds.append(("EX", i, e[i], (sub(e, i), f1, m + 1)))
+                kind = "ket"
+            else:
+                i = pick(e)
+                e1 = sub(e, i)
+                preds = [("PA", i, (e1, f, m)), ("WP", i, (e1, f, m + 1))]
+                if e1[i] > 0:
+                    e2 = sub(e1, i)
+                    preds.append(("E2", i, e1[i], (e2, f, m), (e2, f, m + 1)))
+                kind = "bra"
+            for p in preds:
+                for x in p:
+                    if isinstance(x, tuple) and len(x) == 3 and isinstance(x[0], tuple):
+                        need(x)
+            seen.add(node)
+            rec[node] = (kind, preds)
+            order.append(node)
+
+        for f in f_t:
+            for e in e_t:
+                need((e, f, 0))
+        cost = sum(_node_flops(rec[n]) for n in order)
+        if best is None or cost < best[0]:
+            best = (cost, rec, order, pol)
+    return best[1], best[2], e_t, f_t, best[0]
+
+
+def _node_flops(r):
+    if r[0] == "base":
+        return 1  # pref * G_m
+    n = 0
+    for p in r[1]:
+        if p[0] in ("QC", "WQ", "PA", "WP"):
+            n += 2
+        elif p[0] in ("F2", "E2"):
+            n += 4
+        elif p[0] == "EX":
+            n += 2
+    return n
+
+
+def emit_vrr(em, la, lb, lc, ld, name, f_targets=None, policy="auto"):
+    rec, order, e_t, f_t, cost = vrr_graph(la, lb, lc, ld, f_targets, policy)
+    T = em.T
+    L = la + lb + lc + ld
+    ids = {n: k for k, n in enumerate(order)}
+    acc_index = {}
+    k = 0
+    for e in e_t:
+        for f in f_t:
+            acc_index[(e, f)] = k
+            k += 1
+    nacc = k
+    ax = "xyz"
+    em.lines.append(f"  __device__ __forceinline__ static void {name}(const {T}* __restrict__ g,")
+    em.lines.append(f"      {T} PAx, {T} PAy, {T} PAz, {T} WPx, {T} WPy, {T} WPz,")
+    em.lines.append(f"      {T} QCx, {T} QCy, {T} QCz, {T} WQx, {T} WQy, {T} WQz,")
+    em.lines.append(f"      {T} i2z, {T} roz, {T} i2e, {T} roe, {T} i2ze, {T}* __restrict__ acc) {{")
+    used = set()
+    for n in order:
+        r = rec[n]
+        e, f, m = n
+        v = f"v{ids[n]}"
+        if r[0] == "base":
+            em.lines.append(f"    const {T} {v} = g[{m}];")
+            continue
+        terms = []
+        for p in r[1]:
+            tag = p[0]
+            if tag in ("QC", "WQ", "PA", "WP"):
+                terms.append(f"{tag}{ax[p[1]]} * v{ids[p[2]]}")
+            elif tag == "F2":
+                c = p[2]
+                coef = "i2e" if c == 1 else f"({em.lit(c)} * i2e)"
+                terms.append(f"{coef} * (v{ids[p[3]]} - roe * v{ids[p[4]]})")
+            elif tag == "E2":
+                c = p[2]
+                coef = "i2z" if c == 1 else f"({em.lit(c)} * i2z)"
+                terms.append(f"{coef} * (v{ids[p[3]]} - roz * v{ids[p[4]]})")
+            elif tag == "EX":
+                c = p[2]
+                coef = "i2ze" if c == 1 else f"({em.lit(c)} * i2ze)"
+                terms.append(f"{coef} * v{ids[p[3]]}")
+        em.lines.append(f"    const {T} {v} = " + " + ".join(terms) + ";")
+    for (e, f), a in acc_index.items():
+        em.lines.append(f"    acc[{a}] += v{ids[(e, f, 0)]};")
+    em.lines.append("  }")
+    return nacc, cost + nacc  # accumulation adds
+
+
+# --------------------------------------------------------- HRR + sph ----
+def hrr_plan(la, lb):
+    """Nodes (e, b) needed for the targets (a, b), |a| = la, |b| = lb, with
+    (e, b+1_i) = (e+1_i, b) + AB_i (e, b)."""
+    rec = {}
+    order = []
+
+    def need(n):
+        if n in rec:
+            return
+        e, b = n
+        if sum(b) == 0:
+            rec[n] = ("base",)
+            order.append(n)
+            return
+        i = [k for k in range(3) if b[k] > 0][0]
+        b1 = sub(b, i)
+        p1, p2 = (add(e, i), b1), (e, b1)
+        need(p1)
+        need(p2)
+        rec[n] = ("hrr", i, p1, p2)
+        order.append(n)
+
+    for a in cart(la):
+        for b in cart(lb):
+            need((a, b))
+    return rec, order
+
+
+def emit_post(em, la, lb, lc, ld, name="post"):
+    """acc[ie*NF + jf] (ie over bra e components la..la+lb, jf over ket f
+    components lc..lc+ld)  ->  out[((as*nbs+bs)*ncs+cs)*nds+ds]."""
+    T = em.T
+    E, F = la + lb, lc + ld
+    e_list = [e for d in range(la, E + 1) for e in cart(d)]
+    f_list = [f for d in range(lc, F + 1) for f in cart(d)]
+    eidx = {e: k for k, e in enumerate(e_list)}
+    fidx = {f: k for k, f in enumerate(f_list)}
+    NF = len(f_list)
+    nas, nbs, ncs, nds = 2 * la + 1, 2 * lb + 1, 2 * lc + 1, 2 * ld + 1
+    ax = "xyz"
+    em.lines.append(f"  __device__ __forceinline__ static void {name}(const {T}* __restrict__ acc,")
+    em.lines.append(f"      {T} ABx, {T} ABy, {T} ABz, {T} CDx, {T} CDy, {T} CDz, {T}* __restrict__ out) {{")
+    flops = 0
+    brec, border = hrr_plan(la, lb)
+    krec, korder = hrr_plan(lc, ld)
+    # bra HRR + bra spherical for every f component
+    for jf in range(NF):
+        names = {}
+        for k, n in enumerate(border):
+            r = brec[n]
+            nm = f"b{jf}_{k}"
+            names[n] = nm
+            if r[0] == "base":
+                names[n] = f"acc[{eidx[n[0]] * NF + jf}]"
+                continue
+            _, i, p1, p2 = r
+            em.lines.append(f"    const {T} {nm} = {names[p1]} + AB{ax[i]} * {names[p2]};")
+            flops += 2
+        for as_ in range(nas):
+            for bs in range(nbs):
+                terms = []
+                for a, ca in SPH[la][as_].items():
+                    for b, cb in SPH[lb][bs].items():
+                        c = ca * cb
+                        nm = names[(a, b)]
+                        terms.append(nm if c == 1.0 else f"{em.lit(c)} * {nm}")
+                        flops += 0 if c == 1.0 else 1
+                flops += len(terms) - 1
+                em.lines.append(f"    const {T} s{as_}_{bs}_{jf} = " + " + ".join(terms) + ";")
+    # ket HRR + ket spherical for every bra spherical pair
+    for as_ in range(nas):
+        for bs in range(nbs):
+            names = {}
+            for k, n in enumerate(korder):
+                r = krec[n]
+                if r[0] == "base":
+                    names[n] = f"s{as_}_{bs}_{fidx[n[0]]}"
+                    continue
+                nm = f"k{as_}_{bs}_{k}"
+                names[n] = nm
+                _, i, p1, p2 = r
+                em.lines.append(f"    const {T} {nm} = {names[p1]} + CD{ax[i]} * {names[p2]};")
+                flops += 2
+            for cs in range(ncs):
+                for ds in range(nds):
+                    terms = []
+                    for c_, cc in SPH[lc][cs].items():
+                        for d_, cd in SPH[ld][ds].items():
+                            c = cc * cd
+                            nm = names[(c_, d_)]
+                            terms.append(nm if c == 1.0 else f"{em.lit(c)} * {nm}")
+                            flops += 0 if c == 1.0 else 1
+                    flops += len(terms) - 1
+                    o = ((as_ * nbs + bs) * ncs + cs) * nds + ds
+                    em.lines.append(f"    out[{o}] = " + " + ".join(terms) + ";")
+    em.lines.append("  }")
+    return flops
+
+
+def split_f(lc, ld, G):
+    """Partition the ket f components into G groups of consecutive components."""
+    f_list = [f for d in range(lc, lc + ld + 1) for f in cart(d)]
+    n = len(f_list)
+    out = []
+    for g in range(G):
+        lo = (g * n) // G
+        hi = ((g + 1) * n) // G
+        out.append(f_list[lo:hi])
+    return out
+
+
+PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+
+
+def class_tag(c):
+    return "".join(str(x) for x in c)
+
+
+def generate(outdir, T="double", splits=None):
+    """Write one header and one translation unit per class into outdir and
+    return the operation-count model."""
+    splits = splits or {}
+    os.makedirs(outdir, exist_ok=True)
+    suffix = "" if T == "double" else "_f32"
+    model = {}
+    for (la, lb, lc, ld) in classes():
+        em = Emitter(T)
+        tag = class_tag((la, lb, lc, ld))
+        em.lines.append("// Generated by gen_eri.py; do not edit.")
+        em.lines.append("#pragma once")
+        E, F = la + lb, lc + ld
+        NE = sum(ncart(d) for d in range(la, E + 1))
+        NF = sum(ncart(d) for d in range(lc, F + 1))
+        nm = f"Eri{tag}{suffix}"
+        em.lines.append(f"struct {nm} {{")
+        em.lines.append(f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {E + F};")
+        em.lines.append(f"  static constexpr int NE = {NE}, NF = {NF}, NACC = {NE * NF};")
+        nsph = (2 * la + 1) * (2 * lb + 1) * (2 * lc + 1) * (2 * ld + 1)
+        em.lines.append(f"  static constexpr int NOUT = {nsph};")
+        _, vflops = emit_vrr(em, la, lb, lc, ld, "vrr")
+        G = splits.get((la, lb, lc, ld), 1)
+        em.lines.append(f"  static constexpr int NSPLIT = {G};")
+        split_cost = []
+        if G > 1:
+            groups = split_f(lc, ld, G)
+            for g, ft in enumerate(groups):
+                _, c = emit_vrr(em, la, lb, lc, ld, f"vrr_part{g}", f_targets=ft)
+                split_cost.append(c)
+        pflops = emit_post(em, la, lb, lc, ld)
+        em.lines.append("};")
+        with open(os.path.join(outdir, f"eri_{tag}{suffix}.h"), "w") as f:
+            f.write("\n".join(em.lines) + "\n")
+        model[tag] = dict(vrr_flops=vflops, post_flops=pflops, nacc=NE * NF,
+                          nout=nsph, split=G, split_vrr_flops=split_cost)
+        diag = (la, lb) == (lc, ld)
+        tu = [
+            "// Generated by gen_eri.py; do not edit.",
+            '#include "hfx_device.hpp"',
+            f'#include "eri_{tag}{suffix}.h"',
+            "namespace hfx {",
+            f"void launch_eri_{tag}(const QuartetArgs &a, unsigned nblk, hipStream_t s) {{",
+            f"  hipLaunchKernelGGL(k_eri<{nm}>, dim3(nblk), dim3(64), 0, s, a);",
+            "}",
+            f"void launch_eval_{tag}(const PairHdr *h, const PrimRec *p, const int32_t *bk, int n, int op,",
+            "                    double om2, const double *tab, double *out, hipStream_t s) {",
+            f"  hipLaunchKernelGGL(k_eval<{nm}>, dim3((n + 63) / 64), dim3(64), 0, s, h, p, bk, n, op, om2, tab, out);",
+            "}",
+        ]
+        if diag:
+            tu += [
+                f"void launch_schwarz_{class_tag((la, lb))}(const PairHdr *h, const PrimRec *p, const int32_t *ids, int n,",
+                "                    int op, double om2, const double *tab, double *Q, hipStream_t s) {",
+                f"  hipLaunchKernelGGL(k_schwarz<{nm}>, dim3((n + 63) / 64), dim3(64), 0, s, h, p, ids, n, op, om2, tab, Q);",
+                "}",
+            ]
+        tu.append("}  // namespace hfx")
+        with open(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "w") as f:
+            f.write("\n".join(tu) + "\n")
+    return model
+
+
+def write_model(outdir, model):
+    """FLOP model table (per primitive quartet: the vertical recurrence; per
+    contracted quartet: horizontal recurrence, spherical transform and the
+    four digestion contractions)."""
+    tags = [class_tag(c) for c in classes()]
+    vr = ", ".join(f"{model[t]['vrr_flops']}.0" for t in tags)
+    po = ", ".join(f"{model[t]['post_flops'] + 8 * model[t]['nout'] + 4}.0" for t in tags)
+    src = [
+        "// Generated by gen_eri.py; do not edit.",
+        "namespace hfx {",
+        f"static const double k_model_vrr[21] = {{{vr}}};",
+        f"static const double k_model_post[21] = {{{po}}};",
+        "const double *model_vrr() { return k_model_vrr; }",
+        "const double *model_post() { return k_model_post; }",
+        "// Arithmetic of one primitive quartet outside the recurrence: geometry",
+        "// (24), Boys Taylor + recursion (15 + 3L per evaluation), prefactor",
+        "// scaling, and for the attenuated kernel the second Boys evaluation and",
+        "// the theta powers.",
+        "double model_prim_overhead(int op, int L) {",
+        "  return 24.0 + (op ? 2 : 1) * (15.0 + 3.0 * L) + (op ? 3 : 1) * (L + 1.0) + (op ? 4.0 : 0.0);",
+        "}",
+        "}  // namespace hfx",
+    ]
+    with open(os.path.join(outdir, "model.hip"), "w") as f:
+        f.write("\n".join(src) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--outdir", required=True)
+    ap.add_argument("--type", default="double")
+    ap.add_argument("--model", default=None)
+    a = ap.parse_args()
+    model = generate(a.outdir, a.type)
+    write_model(a.outdir, model)
+    if a.model:
+        with open(a.model, "w") as f:
+            json.dump(model, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

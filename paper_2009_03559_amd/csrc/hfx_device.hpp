@@ -1,0 +1,330 @@
+// Device-side building blocks of the screened exchange build (gfx950).
+//
+// Data layout in HBM
+//   PairHdr  one per shell pair (I >= J, A = the shell of higher l): offset
+//            and count of its primitive-pair records, function offsets of A
+//            and B, A-B, and whether I == J.
+//   PrimRec  one per primitive pair (a, b): zeta = a + b, 1/(2 zeta), the
+//            Gaussian product centre P, P - A and the scaled prefactor
+//            sqrt(2) pi^(5/4) c_a c_b exp(-a b |AB|^2 / zeta) / zeta, so that
+//            the [00|00] prefactor 2 pi^(5/2)/(zeta eta sqrt(zeta+eta)) K_AB
+//            K_CD is the product of two records over sqrt(zeta + eta).
+//   Boys     table T_L[i][k] = F_(L+k)(i h) / k!, h = 1/16, i <= 576, k < 8,
+//            one 8-double row per grid point and L.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hfx {
+
+struct PairHdr {
+    int32_t off;   // first PrimRec
+    int32_t n;     // number of PrimRecs
+    int32_t bfA;   // first spherical function of shell A
+    int32_t bfB;   // first spherical function of shell B
+    double ABx, ABy, ABz;
+    int32_t diag;  // I == J
+    int32_t id;    // global pair id
+};
+
+struct PrimRec {
+    double z, i2z, Px, Py, Pz, PAx, PAy, PAz, K, pad;
+};
+
+constexpr int BOYS_NROW = 577;          // grid points 0 .. 36 step 1/16
+constexpr double BOYS_H = 1.0 / 16.0;
+constexpr double BOYS_INVH = 16.0;
+constexpr double BOYS_TMAX = 36.0;
+constexpr int BOYS_NTAY = 8;            // Taylor terms
+constexpr int BOYS_LMAX = 8;            // highest L = 4 * lmax
+constexpr int BOYS_TAB_SIZE = (BOYS_LMAX + 1) * BOYS_NROW * BOYS_NTAY;
+
+// F_m(x), m = 0..L.  x < 36: Taylor expansion of F_L around the nearest grid
+// point from the table, then the downward recursion
+// F_m = (2x F_(m+1) + e^-x) / (2m+1).  x >= 36: F_0 = sqrt(pi/(4x)) (erf(sqrt x)
+// equals 1 to 2e-17 there), then the upward recursion
+// F_(m+1) = ((2m+1) F_m - e^-x) / (2x), stable for x > L.
+template <int L>
+__device__ __forceinline__ void boys(double x, const double *__restrict__ tab, double *F) {
+    const double ex = exp(-x);
+    if (x < BOYS_TMAX) {
+        const int i = __double2int_rn(x * BOYS_INVH);
+        const double u = i * BOYS_H - x;
+        const double *r = tab + ((size_t)L * BOYS_NROW + i) * BOYS_NTAY;
+        const double4 lo = *reinterpret_cast<const double4 *>(r);
+        const double4 hi = *reinterpret_cast<const double4 *>(r + 4);
+        double f = hi.w;
+        f = fma(f, u, hi.z);
+        f = fma(f, u, hi.y);
+        f = fma(f, u, hi.x);
+        f = fma(f, u, lo.w);
+        f = fma(f, u, lo.z);
+        f = fma(f, u, lo.y);
+        f = fma(f, u, lo.x);
+        F[L] = f;
+        const double x2 = 2.0 * x;
+#pragma unroll
+        for (int m = L - 1; m >= 0; --m) F[m] = fma(x2, F[m + 1], ex) * (1.0 / (2 * m + 1));
+    } else {
+        const double rs = rsqrt(x);
+        F[0] = 0.88622692545275801365 * rs;  // sqrt(pi)/2
+        const double h = 0.5 * rs * rs;       // 1/(2x)
+#pragma unroll
+        for (int m = 0; m < L; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -ex) * h;
+    }
+}
+
+// One primitive quartet of class C: geometry, kernel function G_m, VRR into acc.
+// op: 0 = 1/r, 1 = erfc(omega r)/r, where G_m = F_m(T) - theta^(2m+1) F_m(theta^2 T),
+// theta^2 = omega^2/(omega^2+rho): the Gaussian transform of the kernel restricted
+// to [omega, inf) maps to the Boys variable interval [theta, 1].
+template <class C>
+__device__ __forceinline__ void prim_quartet(const PrimRec &b, double kz, double ki2z, double kPx,
+                                             double kPy, double kPz, double kQCx, double kQCy,
+                                             double kQCz, double kK, int op, double om2,
+                                             const double *__restrict__ tab, double *acc) {
+    const double ze = b.z + kz;
+    const double rs = rsqrt(ze);
+    const double ize = rs * rs;
+    const double rho = b.z * kz * ize;
+    const double PQx = b.Px - kPx, PQy = b.Py - kPy, PQz = b.Pz - kPz;
+    const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    const double pref = b.K * kK * rs;
+    double g[C::L + 1];
+    boys<C::L>(T, tab, g);
+    if (op) {
+        const double tr = rsqrt(om2 + rho);
+        const double th = sqrt(om2) * tr;   // theta
+        const double th2 = th * th;
+        double g2[C::L + 1];
+        boys<C::L>(th2 * T, tab, g2);
+        double f = th * pref;
+#pragma unroll
+        for (int m = 0; m <= C::L; ++m) {
+            g[m] = fma(-f, g2[m], pref * g[m]);
+            f *= th2;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m <= C::L; ++m) g[m] *= pref;
+    }
+    const double re = kz * ize, rz = b.z * ize;  // rho/zeta, rho/eta
+    C::vrr(g, b.PAx, b.PAy, b.PAz, -re * PQx, -re * PQy, -re * PQz, kQCx, kQCy, kQCz,
+           rz * PQx, rz * PQy, rz * PQz, b.i2z, re, ki2z, rz, 0.5 * ize, acc);
+}
+
+// Digestion of one contracted quartet (AB|CD) with spherical values v[a][b][c][d]:
+//   K'_ac += d v P_bd,  K'_ad += d v P_bc,  K'_bc += d v P_ad,  K'_bd += d v P_ac
+// (four of the eight permutation images; the other four are the transposes,
+// added by K = K' + K'^T).  FP64 atomics into K'.
+template <int NA, int NB, int NC, int ND>
+__device__ __forceinline__ void digest(const double *__restrict__ v, int a0, int b0, int c0, int d0,
+                                       double deg, const double *__restrict__ P, double *K,
+                                       int64_t ld) {
+    double Pbd[NB][ND], Pbc[NB][NC], Pad[NA][ND], Pac[NA][NC];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) Pbd[b][d] = P[(int64_t)(b0 + b) * ld + d0 + d];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Pbc[b][c] = P[(int64_t)(b0 + b) * ld + c0 + c];
+    }
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) Pad[a][d] = P[(int64_t)(a0 + a) * ld + d0 + d];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Pac[a][c] = P[(int64_t)(a0 + a) * ld + c0 + c];
+    }
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) s = fma(v[((a * NB + b) * NC + c) * ND + d], Pbd[b][d], s);
+            atomicAdd(&K[(int64_t)(a0 + a) * ld + c0 + c], deg * s);
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) s = fma(v[((a * NB + b) * NC + c) * ND + d], Pbc[b][c], s);
+            atomicAdd(&K[(int64_t)(a0 + a) * ld + d0 + d], deg * s);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) s = fma(v[((a * NB + b) * NC + c) * ND + d], Pad[a][d], s);
+            atomicAdd(&K[(int64_t)(b0 + b) * ld + c0 + c], deg * s);
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) s = fma(v[((a * NB + b) * NC + c) * ND + d], Pac[a][c], s);
+            atomicAdd(&K[(int64_t)(b0 + b) * ld + d0 + d], deg * s);
+        }
+    }
+}
+
+// Launch parameters of one class pair (bra class cb >= ket class ck).
+struct QuartetArgs {
+    const PairHdr *hdr;
+    const PrimRec *prim;
+    const int32_t *bra_ids;   // bra class: pair ids sorted by (group, -Q)
+    const double *bra_Q;
+    const int32_t *bra_grp;   // group index of each bra slot
+    int32_t n_bra;
+    const int32_t *ket_ids;   // ket class, same order
+    const double *ket_Q;
+    const int32_t *ket_goff;  // n_kgrp + 1 group offsets into the ket list
+    const int32_t *ket_gnp;   // primitive-pair count of each ket group
+    int32_t n_kgrp;
+    int32_t same;             // bra class == ket class: quartet (p,q) needs q <= p
+    double tau;
+    int32_t op;
+    double om2;               // omega^2
+    const double *boys;
+    const double *P;
+    double *K;
+    int64_t ld;
+    unsigned long long *count;  // [0] quartets, [1] primitive quartets
+};
+
+// Ket range of block (p, g): slots [lo, cut) of ket group g with Q_p Q_q >= tau.
+__device__ __forceinline__ int ket_cut(const QuartetArgs &a, int p, int g, int *lo_out) {
+    const double Qp = a.bra_Q[p];
+    int lo = a.ket_goff[g], hi = a.ket_goff[g + 1];
+    *lo_out = lo;
+    if (a.same) {
+        const int gp = a.bra_grp[p];
+        if (g > gp) return lo;  // empty: every slot of group g is after p
+        if (g == gp) hi = p + 1;
+    }
+    // Q descending: first q with !(Qp*Q[q] >= tau)
+    int l = lo, h = hi;
+    while (l < h) {
+        const int m = (l + h) >> 1;
+        if (Qp * a.ket_Q[m] >= a.tau) l = m + 1;
+        else h = m;
+    }
+    return l;
+}
+
+// Lane-per-quartet kernel of class C: block = one bra pair and one ket group,
+// 64 lanes walk the screened ket range; bra primitive data is uniform.
+template <class C>
+__global__ __launch_bounds__(64) void k_eri(QuartetArgs a) {
+    const int p = blockIdx.x / a.n_kgrp;
+    const int g = blockIdx.x - p * a.n_kgrp;
+    if (p >= a.n_bra) return;
+    int lo = 0;
+    const int cut = ket_cut(a, p, g, &lo);
+    if (cut <= lo) return;
+    const PairHdr bh = a.hdr[a.bra_ids[p]];
+    const int nkp = a.ket_gnp[g];
+    const int lane = threadIdx.x;
+    if (lane == 0 && a.count) {
+        const unsigned long long nq = (unsigned long long)(cut - lo);
+        atomicAdd(&a.count[0], nq);
+        atomicAdd(&a.count[1], nq * (unsigned long long)(bh.n * nkp));
+    }
+    constexpr int NA = 2 * C::LA + 1, NB = 2 * C::LB + 1, NC = 2 * C::LC + 1, ND = 2 * C::LD + 1;
+    for (int q0 = lo; q0 < cut; q0 += 64) {
+        const int q = q0 + lane;
+        const bool act = q < cut;
+        const int kid = a.ket_ids[act ? q : lo];
+        const PairHdr kh = a.hdr[kid];
+        double acc[C::NACC];
+#pragma unroll
+        for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
+        for (int kp = 0; kp < nkp; ++kp) {
+            const PrimRec k = a.prim[kh.off + kp];
+            for (int bp = 0; bp < bh.n; ++bp) {
+                const PrimRec b = a.prim[bh.off + bp];
+                prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, a.op, a.om2,
+                                a.boys, acc);
+            }
+        }
+        double out[C::NOUT];
+        C::post(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, out);
+        if (act) {
+            double deg = 1.0;
+            if (bh.diag) deg *= 0.5;
+            if (kh.diag) deg *= 0.5;
+            if (bh.id == kh.id) deg *= 0.5;
+            digest<NA, NB, NC, ND>(out, bh.bfA, bh.bfB, kh.bfA, kh.bfB, deg, a.P, a.K, a.ld);
+        }
+    }
+}
+
+// Schwarz factor of each pair of one pair class: Q = sqrt(max diagonal (ij|ij)).
+template <class C>
+__global__ __launch_bounds__(64) void k_schwarz(const PairHdr *__restrict__ hdr,
+                                                const PrimRec *__restrict__ prim,
+                                                const int32_t *__restrict__ ids, int n, int op,
+                                                double om2, const double *__restrict__ tab,
+                                                double *__restrict__ Q) {
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t >= n) return;
+    const PairHdr h = hdr[ids[t]];
+    double acc[C::NACC];
+#pragma unroll
+    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
+    for (int kp = 0; kp < h.n; ++kp) {
+        const PrimRec k = prim[h.off + kp];
+        for (int bp = 0; bp < h.n; ++bp) {
+            const PrimRec b = prim[h.off + bp];
+            prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc);
+        }
+    }
+    double out[C::NOUT];
+    C::post(acc, h.ABx, h.ABy, h.ABz, h.ABx, h.ABy, h.ABz, out);
+    constexpr int NA = 2 * C::LA + 1, NB = 2 * C::LB + 1;
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) mx = fmax(mx, out[((i * NB + j) * NA + i) * NB + j]);
+    Q[h.id] = sqrt(mx);
+}
+
+// Raw integrals of listed quartets (canonical pair ids bra, ket), one per lane.
+template <class C>
+__global__ __launch_bounds__(64) void k_eval(const PairHdr *__restrict__ hdr,
+                                             const PrimRec *__restrict__ prim,
+                                             const int32_t *__restrict__ bk, int n, int op, double om2,
+                                             const double *__restrict__ tab, double *__restrict__ out) {
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t >= n) return;
+    const PairHdr bh = hdr[bk[2 * t]], kh = hdr[bk[2 * t + 1]];
+    double acc[C::NACC];
+#pragma unroll
+    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
+    for (int kp = 0; kp < kh.n; ++kp) {
+        const PrimRec k = prim[kh.off + kp];
+        for (int bp = 0; bp < bh.n; ++bp) {
+            const PrimRec b = prim[bh.off + bp];
+            prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc);
+        }
+    }
+    double v[C::NOUT];
+    C::post(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, v);
+#pragma unroll
+    for (int i = 0; i < C::NOUT; ++i) out[(int64_t)t * C::NOUT + i] = v[i];
+}
+
+}  // namespace hfx

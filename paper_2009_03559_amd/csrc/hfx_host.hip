@@ -1,0 +1,740 @@
+// libhfx host side: basis setup, pair enumeration, Schwarz bounds, screened
+// class-sorted quartet lists and the launch sequence of the exchange build.
+//
+// Paper mapping (Sec. 3): contracted shells; pair lists preselected with the
+// Schwarz factors; per-quartet Schwarz screening; 8-fold symmetry (unique
+// quartets plus degeneracy factors, digestion of four images and K = K' + K'^T);
+// Cartesian->spherical transform.  The static MPI shell-pair / shell-quartet
+// distributions of Sec. 3.1 are replaced by one GPU grid over
+// (bra pair, ket group) whose ket range is cut by binary search on the
+// Q-sorted list: the screened quartet set is never materialised.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hfx.h"
+#include "hfx_device.hpp"
+#include "hfx_internal.hpp"
+
+namespace hfx {
+
+thread_local std::string g_err;
+
+hfx_status fail(hfx_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(x)                                                                      \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess)                                                          \
+            return fail(HFX_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+// ---------------------------------------------------------------- Boys ----
+// F_m(x) on the grid x_i = i/16, m = 0..15, in long double: the top order by
+// its power series  F_M(x) = e^-x sum_k (2x)^k / ((2M+1)(2M+3)...(2M+2k+1)),
+// the lower orders by the stable downward recursion.  Stored as
+// T_L[i][k] = F_(L+k)(x_i) / k!.
+static std::vector<double> make_boys_table() {
+    const int M = BOYS_LMAX + BOYS_NTAY - 1;
+    std::vector<double> tab((size_t)BOYS_TAB_SIZE);
+    std::vector<long double> F(M + 1);
+    for (int i = 0; i < BOYS_NROW; ++i) {
+        long double x = (long double)i / 16.0L;
+        long double term = 1.0L / (2 * M + 1), sum = term;
+        for (int k = 1; k < 4000; ++k) {
+            term *= 2.0L * x / (2 * M + 2 * k + 1);
+            sum += term;
+            if (term < 1e-22L * sum) break;
+        }
+        long double ex = expl(-x);
+        F[M] = ex * sum;
+        for (int m = M - 1; m >= 0; --m) F[m] = (2.0L * x * F[m + 1] + ex) / (2 * m + 1);
+        for (int L = 0; L <= BOYS_LMAX; ++L) {
+            long double fact = 1.0L;
+            for (int k = 0; k < BOYS_NTAY; ++k) {
+                if (k > 0) fact *= k;
+                tab[((size_t)L * BOYS_NROW + i) * BOYS_NTAY + k] = (double)(F[L + k] / fact);
+            }
+        }
+    }
+    return tab;
+}
+
+static std::mutex g_boys_mu;
+static std::vector<double *> g_boys_dev;  // per device
+
+static hfx_status boys_table(const double **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_boys_mu);
+    if ((int)g_boys_dev.size() <= dev) g_boys_dev.resize(dev + 1, nullptr);
+    if (!g_boys_dev[dev]) {
+        std::vector<double> t = make_boys_table();
+        double *d = nullptr;
+        HIPCHK(hipMalloc(&d, t.size() * sizeof(double)));
+        HIPCHK(hipMemcpy(d, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+        g_boys_dev[dev] = d;
+    }
+    *out = g_boys_dev[dev];
+    return HFX_OK;
+}
+
+// ------------------------------------------------------------ kernels ----
+// Primitive-pair records of every pair.
+struct ShellDev {
+    double x, y, z;
+    int32_t nprim, off;
+};
+
+__global__ void k_pairdata(const PairHdr *__restrict__ hdr, const int32_t *__restrict__ shA,
+                           const int32_t *__restrict__ shB, const ShellDev *__restrict__ sh,
+                           const double *__restrict__ ex, const double *__restrict__ cn, int64_t npair,
+                           PrimRec *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npair) return;
+    const PairHdr h = hdr[t];
+    const ShellDev A = sh[shA[t]], B = sh[shB[t]];
+    const double ab2 = h.ABx * h.ABx + h.ABy * h.ABy + h.ABz * h.ABz;
+    const double c0 = 5.914967172795613;  // sqrt(2) pi^(5/4)
+    int r = h.off;
+    for (int i = 0; i < A.nprim; ++i) {
+        const double a = ex[A.off + i], ca = cn[A.off + i];
+        for (int j = 0; j < B.nprim; ++j) {
+            const double b = ex[B.off + j], cb = cn[B.off + j];
+            const double z = a + b, iz = 1.0 / z;
+            PrimRec p;
+            p.z = z;
+            p.i2z = 0.5 * iz;
+            p.Px = (a * A.x + b * B.x) * iz;
+            p.Py = (a * A.y + b * B.y) * iz;
+            p.Pz = (a * A.z + b * B.z) * iz;
+            p.PAx = p.Px - A.x;
+            p.PAy = p.Py - A.y;
+            p.PAz = p.Pz - A.z;
+            p.K = c0 * ca * cb * exp(-a * b * iz * ab2) * iz;
+            p.pad = 0.0;
+            out[r++] = p;
+        }
+    }
+}
+
+__global__ void k_fill(double *K, int64_t n, int64_t ld) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * n) return;
+    K[(t / n) * ld + t % n] = 0.0;
+}
+
+__global__ void k_fill_u64(unsigned long long *c, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) c[t] = 0ull;
+}
+
+// K = K' + K'^T in place; one thread per (i, j) with j >= i.
+__global__ void k_symmetrize(double *K, int64_t n, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.y * 16 + threadIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * 16 + threadIdx.x;
+    if (i >= n || j >= n || j < i) return;
+    const double s = K[i * ld + j] + K[j * ld + i];
+    K[i * ld + j] = s;
+    K[j * ld + i] = s;
+}
+
+// Per-block max |P_ij - P_ji| and max |P_ij|.
+__global__ void k_asym(const double *P, int64_t n, int64_t ld, double *part) {
+    __shared__ double s0[256], s1[256];
+    double m0 = 0.0, m1 = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n * n; t += (int64_t)gridDim.x * 256) {
+        const int64_t i = t / n, j = t % n;
+        const double a = P[i * ld + j];
+        m0 = fmax(m0, fabs(a - P[j * ld + i]));
+        m1 = fmax(m1, fabs(a));
+    }
+    s0[threadIdx.x] = m0;
+    s1[threadIdx.x] = m1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + w]);
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+// ----------------------------------------------------- class dispatch ----
+#define HFX_FOR_CLASSES(X) \
+    X(0000) X(1000) X(1010) X(1100) X(1110) X(1111) X(2000) X(2010) X(2011) X(2020) X(2100) \
+    X(2110) X(2111) X(2120) X(2121) X(2200) X(2210) X(2211) X(2220) X(2221) X(2222)
+#define DECL(T)                                                                                  \
+    void launch_eri_##T(const QuartetArgs &, unsigned, hipStream_t);                            \
+    void launch_eval_##T(const PairHdr *, const PrimRec *, const int32_t *, int, int, double,   \
+                         const double *, double *, hipStream_t);
+HFX_FOR_CLASSES(DECL)
+#undef DECL
+void launch_schwarz_00(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
+void launch_schwarz_10(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
+void launch_schwarz_11(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
+void launch_schwarz_20(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
+void launch_schwarz_21(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
+void launch_schwarz_22(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
+
+typedef void (*eri_fn)(const QuartetArgs &, unsigned, hipStream_t);
+typedef void (*eval_fn)(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *,
+                        double *, hipStream_t);
+typedef void (*schwarz_fn)(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *,
+                           double *, hipStream_t);
+
+// class index cb(cb+1)/2 + ck, pair classes ss ps pp ds dp dd
+static const eri_fn k_eri_tab[21] = {
+#define E(T) launch_eri_##T,
+    HFX_FOR_CLASSES(E)
+#undef E
+};
+static const eval_fn k_eval_tab[21] = {
+#define E(T) launch_eval_##T,
+    HFX_FOR_CLASSES(E)
+#undef E
+};
+static const schwarz_fn k_schwarz_tab[6] = {launch_schwarz_00, launch_schwarz_10, launch_schwarz_11,
+                                            launch_schwarz_20, launch_schwarz_21, launch_schwarz_22};
+
+const int PAIR_L[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
+
+// -------------------------------------------------------------- pairs ----
+static void nrm_coefs(const std::vector<hfx_shell> &sh, const double *exps, const double *coefs,
+                      std::vector<double> &cn) {
+    // Coefficients multiply primitives normalised like x^l exp(-a r^2):
+    //   N(a, l) = (2a/pi)^(3/4) (4a)^(l/2) / sqrt((2l-1)!!),
+    // then the contraction is scaled to unit self-overlap, using the overlap
+    // of two such primitives of the same l on one centre,
+    //   [2 sqrt(a b)/(a+b)]^(l + 3/2).
+    static const double df[3] = {1.0, 1.0, 3.0};
+    for (const hfx_shell &s : sh) {
+        for (int i = 0; i < s.nprim; ++i) {
+            const double a = exps[s.prim_off + i];
+            cn[s.prim_off + i] = coefs[s.prim_off + i] * std::pow(2.0 * a / M_PI, 0.75) *
+                                 std::pow(4.0 * a, 0.5 * s.l) / std::sqrt(df[s.l]);
+        }
+        double ss = 0.0;
+        for (int i = 0; i < s.nprim; ++i)
+            for (int j = 0; j < s.nprim; ++j) {
+                const double a = exps[s.prim_off + i], b = exps[s.prim_off + j];
+                ss += coefs[s.prim_off + i] * coefs[s.prim_off + j] *
+                      std::pow(2.0 * std::sqrt(a * b) / (a + b), s.l + 1.5);
+            }
+        const double f = 1.0 / std::sqrt(ss);
+        for (int i = 0; i < s.nprim; ++i) cn[s.prim_off + i] *= f;
+    }
+}
+
+static hfx_status check_opts(const hfx_opts *o) {
+    if (!o) return fail(HFX_EINVAL, "opts is NULL");
+    if (!(o->tau >= 0.0) || !std::isfinite(o->tau)) return fail(HFX_EINVAL, "tau must be finite and >= 0");
+    if (o->op != HFX_OP_COULOMB && o->op != HFX_OP_ERFC) return fail(HFX_EINVAL, "unknown operator");
+    if (!(o->omega >= 0.0) || !std::isfinite(o->omega)) return fail(HFX_EINVAL, "omega must be finite and >= 0");
+    if (o->prec != HFX_PREC_FP64 && o->prec != HFX_PREC_MIXED) return fail(HFX_EINVAL, "unknown precision mode");
+    if (o->prec == HFX_PREC_MIXED && !(o->mixed_cut >= 0.0)) return fail(HFX_EINVAL, "mixed_cut must be >= 0");
+    if (o->prim_tau != 0.0) return fail(HFX_EINVAL, "prim_tau is reserved and must be 0");
+    if (o->flags != 0) return fail(HFX_EINVAL, "flags are reserved and must be 0");
+    return HFX_OK;
+}
+
+int kernel_op(const hfx_opts *o) { return (o->op == HFX_OP_ERFC && o->omega > 0.0) ? 1 : 0; }
+
+}  // namespace hfx
+
+using namespace hfx;
+
+extern "C" const char *hfx_last_error(void) { return g_err.c_str(); }
+
+extern "C" hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, const hfx_shell *shells,
+                                            int32_t nshell, const double *exps, const double *coefs,
+                                            const hfx_opts *o, void *stream, hfx_pairs *out) {
+    if (!out) return fail(HFX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!xyz || !shells || !exps || !coefs) return fail(HFX_EINVAL, "NULL input array");
+    if (natom < 1 || nshell < 1) return fail(HFX_EINVAL, "natom and nshell must be >= 1");
+    if (o) {
+        hfx_status s = check_opts(o);
+        if (s != HFX_OK) return s;
+    }
+    for (int i = 0; i < 3 * natom; ++i)
+        if (!std::isfinite(xyz[i])) return fail(HFX_EINVAL, "non-finite coordinate");
+    int64_t nprim_tot = 0;
+    for (int s = 0; s < nshell; ++s) {
+        const hfx_shell &h = shells[s];
+        if (h.atom < 0 || h.atom >= natom) return fail(HFX_EINVAL, "shell atom index out of range");
+        if (h.l < 0) return fail(HFX_EINVAL, "negative l");
+        if (h.l > HFX_MAX_L) return fail(HFX_EUNSUPPORTED, "l > 2 is not supported");
+        if (h.nprim < 1) return fail(HFX_EINVAL, "nprim < 1");
+        if (h.nprim > HFX_MAX_PRIM) return fail(HFX_EUNSUPPORTED, "nprim > HFX_MAX_PRIM");
+        if (h.prim_off < 0) return fail(HFX_EINVAL, "negative prim_off");
+        nprim_tot = std::max<int64_t>(nprim_tot, (int64_t)h.prim_off + h.nprim);
+    }
+    for (int s = 0; s < nshell; ++s)
+        for (int i = 0; i < shells[s].nprim; ++i) {
+            const double a = exps[shells[s].prim_off + i], c = coefs[shells[s].prim_off + i];
+            if (!(a > 0.0) || !std::isfinite(a)) return fail(HFX_EINVAL, "exponent must be finite and > 0");
+            if (!std::isfinite(c)) return fail(HFX_EINVAL, "non-finite contraction coefficient");
+        }
+    std::unique_ptr<hfx_pairs_s> P(new hfx_pairs_s());
+    P->natom = natom;
+    P->nshell = nshell;
+    P->stream = (hipStream_t)stream;
+    P->sh.assign(shells, shells + nshell);
+    P->xyz.assign(xyz, xyz + 3 * natom);
+    P->exps.assign(exps, exps + nprim_tot);
+    P->cn.assign(nprim_tot, 0.0);
+    nrm_coefs(P->sh, exps, coefs, P->cn);
+    P->bfo.resize(nshell + 1);
+    P->bfo[0] = 0;
+    for (int s = 0; s < nshell; ++s) P->bfo[s + 1] = P->bfo[s] + 2 * shells[s].l + 1;
+    P->nbf = P->bfo[nshell];
+    const int64_t npair = (int64_t)nshell * (nshell + 1) / 2;
+    P->npair = npair;
+    std::vector<PairHdr> hdr(npair);
+    std::vector<int32_t> shA(npair), shB(npair);
+    P->pcls.resize(npair);
+    int64_t rec = 0;
+    for (int I = 0; I < nshell; ++I)
+        for (int J = 0; J <= I; ++J) {
+            const int64_t id = (int64_t)I * (I + 1) / 2 + J;
+            const bool sw = shells[J].l > shells[I].l;
+            const int a = sw ? J : I, b = sw ? I : J;
+            PairHdr h;
+            h.off = (int32_t)rec;
+            h.n = shells[a].nprim * shells[b].nprim;
+            h.bfA = P->bfo[a];
+            h.bfB = P->bfo[b];
+            const double *A = xyz + 3 * shells[a].atom, *B = xyz + 3 * shells[b].atom;
+            h.ABx = A[0] - B[0];
+            h.ABy = A[1] - B[1];
+            h.ABz = A[2] - B[2];
+            h.diag = (I == J);
+            h.id = (int32_t)id;
+            hdr[id] = h;
+            shA[id] = a;
+            shB[id] = b;
+            const int la = shells[a].l, lb = shells[b].l;
+            P->pcls[id] = (int8_t)(la * (la + 1) / 2 + lb);
+            rec += h.n;
+        }
+    if (rec > INT32_MAX || npair > INT32_MAX) return fail(HFX_EUNSUPPORTED, "too many primitive pairs");
+    P->nrec = rec;
+    P->hdr_host = hdr;
+    for (int64_t id = 0; id < npair; ++id) P->class_ids[P->pcls[id]].push_back((int32_t)id);
+    std::vector<ShellDev> shd(nshell);
+    for (int s = 0; s < nshell; ++s) {
+        shd[s].x = xyz[3 * shells[s].atom];
+        shd[s].y = xyz[3 * shells[s].atom + 1];
+        shd[s].z = xyz[3 * shells[s].atom + 2];
+        shd[s].nprim = shells[s].nprim;
+        shd[s].off = shells[s].prim_off;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *d_shA = nullptr, *d_shB = nullptr;
+    ShellDev *d_sh = nullptr;
+    double *d_ex = nullptr, *d_cn = nullptr;
+    auto cleanup = [&]() {
+        hipFree(d_shA);
+        hipFree(d_shB);
+        hipFree(d_sh);
+        hipFree(d_ex);
+        hipFree(d_cn);
+    };
+#define ALLOC(ptr, bytes)                                                        \
+    do {                                                                         \
+        if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                 \
+            cleanup();                                                           \
+            return fail(HFX_ENOMEM, "device allocation of pair data failed");    \
+        }                                                                        \
+    } while (0)
+    ALLOC(P->d_hdr, npair * sizeof(PairHdr));
+    ALLOC(P->d_prim, std::max<int64_t>(rec, 1) * sizeof(PrimRec));
+    ALLOC(P->d_Q, npair * sizeof(double));
+    ALLOC(d_shA, npair * sizeof(int32_t));
+    ALLOC(d_shB, npair * sizeof(int32_t));
+    ALLOC(d_sh, nshell * sizeof(ShellDev));
+    ALLOC(d_ex, std::max<int64_t>(nprim_tot, 1) * sizeof(double));
+    ALLOC(d_cn, std::max<int64_t>(nprim_tot, 1) * sizeof(double));
+#undef ALLOC
+    P->dev_bytes = npair * (sizeof(PairHdr) + sizeof(double)) + rec * sizeof(PrimRec);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(P->d_hdr, hdr.data(), npair * sizeof(PairHdr), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_shA, shA.data(), npair * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_shB, shB.data(), npair * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_sh, shd.data(), nshell * sizeof(ShellDev), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_ex, P->exps.data(), nprim_tot * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_cn, P->cn.data(), nprim_tot * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pairdata, dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st, P->d_hdr, d_shA,
+                           d_shB, d_sh, d_ex, d_cn, npair, P->d_prim);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("pair data: ") + hipGetErrorString(e));
+    const double *tab = nullptr;
+    hfx_status s = boys_table(&tab);
+    if (s != HFX_OK) return s;
+    P->d_boys = tab;
+    *out = P.release();
+    return HFX_OK;
+}
+
+hfx_pairs_s::~hfx_pairs_s() {
+    hipFree(d_hdr);
+    hipFree(d_prim);
+    hipFree(d_Q);
+    drop_lists();
+    hipFree(d_count);
+}
+
+void hfx_pairs_s::drop_lists() {
+    for (auto &c : lists) {
+        hipFree(c.d_ids);
+        hipFree(c.d_Q);
+        hipFree(c.d_grp);
+        hipFree(c.d_goff);
+        hipFree(c.d_gnp);
+        c = ClassList();
+    }
+    lists_valid = false;
+}
+
+extern "C" void hfx_pairs_destroy(hfx_pairs p) { delete p; }
+extern "C" int64_t hfx_pairs_nbf(hfx_pairs p) { return p ? p->nbf : -1; }
+extern "C" int64_t hfx_pairs_npair(hfx_pairs p) { return p ? p->npair : -1; }
+extern "C" int64_t hfx_pairs_device_bytes(hfx_pairs p) { return p ? p->dev_bytes : -1; }
+
+namespace hfx {
+
+hfx_status compute_bounds(hfx_pairs p, const hfx_opts *o, hipStream_t st) {
+    const int op = kernel_op(o);
+    const double om2 = op ? o->omega * o->omega : 0.0;
+    if (p->have_Q && p->q_op == op && p->q_om2 == om2) return HFX_OK;
+    p->drop_lists();
+    int32_t *d_ids = nullptr;
+    size_t mx = 0;
+    for (int c = 0; c < 6; ++c) mx = std::max(mx, p->class_ids[c].size());
+    HIPCHK(hipMalloc(&d_ids, std::max<size_t>(mx, 1) * sizeof(int32_t) * 6));
+    size_t off = 0;
+    for (int c = 0; c < 6; ++c) {
+        const auto &ids = p->class_ids[c];
+        if (ids.empty()) continue;
+        hipError_t e = hipMemcpyAsync(d_ids + off, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            hipFree(d_ids);
+            return fail(HFX_EDEVICE, std::string("bounds copy: ") + hipGetErrorString(e));
+        }
+        k_schwarz_tab[c](p->d_hdr, p->d_prim, d_ids + off, (int)ids.size(), op, om2, p->d_boys, p->d_Q, st);
+        off += mx;
+    }
+    hipError_t e = hipGetLastError();
+    p->Q.resize(p->npair);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->Q.data(), p->d_Q, p->npair * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(d_ids);
+    if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("bounds: ") + hipGetErrorString(e));
+    p->have_Q = true;
+    p->q_op = op;
+    p->q_om2 = om2;
+    return HFX_OK;
+}
+
+// Kept pairs of every class sorted by (primitive-pair count, -Q, id); groups =
+// runs of equal primitive-pair count, so every lane of a block loops the same
+// number of ket primitive pairs.
+hfx_status build_lists(hfx_pairs p, double tau, hipStream_t st) {
+    if (p->lists_valid && p->list_tau == tau) return HFX_OK;
+    p->drop_lists();
+    double qmax = 0.0;
+    for (double q : p->Q) qmax = std::max(qmax, q);
+    p->qmax = qmax;
+    for (int c = 0; c < 6; ++c) {
+        std::vector<int32_t> ids;
+        for (int32_t id : p->class_ids[c])
+            if (p->Q[id] * qmax >= tau) ids.push_back(id);
+        std::sort(ids.begin(), ids.end(), [&](int32_t x, int32_t y) {
+            const int nx = p->hdr_host[x].n, ny = p->hdr_host[y].n;
+            if (nx != ny) return nx < ny;
+            if (p->Q[x] != p->Q[y]) return p->Q[x] > p->Q[y];
+            return x < y;
+        });
+        ClassList &L = p->lists[c];
+        L.n = (int)ids.size();
+        if (!L.n) continue;
+        std::vector<double> q(L.n);
+        std::vector<int32_t> grp(L.n);
+        L.goff.clear();
+        L.gnp.clear();
+        for (int i = 0; i < L.n; ++i) {
+            q[i] = p->Q[ids[i]];
+            const int np = p->hdr_host[ids[i]].n;
+            if (L.gnp.empty() || L.gnp.back() != np) {
+                L.gnp.push_back(np);
+                L.goff.push_back(i);
+            }
+            grp[i] = (int)L.gnp.size() - 1;
+        }
+        L.goff.push_back(L.n);
+        L.ngrp = (int)L.gnp.size();
+        HIPCHK(hipMalloc(&L.d_ids, L.n * sizeof(int32_t)));
+        HIPCHK(hipMalloc(&L.d_Q, L.n * sizeof(double)));
+        HIPCHK(hipMalloc(&L.d_grp, L.n * sizeof(int32_t)));
+        HIPCHK(hipMalloc(&L.d_goff, L.goff.size() * sizeof(int32_t)));
+        HIPCHK(hipMalloc(&L.d_gnp, L.gnp.size() * sizeof(int32_t)));
+        HIPCHK(hipMemcpyAsync(L.d_ids, ids.data(), L.n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.d_Q, q.data(), L.n * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.d_grp, grp.data(), L.n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.d_goff, L.goff.data(), L.goff.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.d_gnp, L.gnp.data(), L.gnp.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        L.h_ids = std::move(ids);
+        L.h_Q = std::move(q);
+        L.h_grp = std::move(grp);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    p->lists_valid = true;
+    p->list_tau = tau;
+    return HFX_OK;
+}
+
+hfx_status check_P(const double *P, int64_t n, int64_t ld, hipStream_t st) {
+    const int nb = (int)std::min<int64_t>(1024, (n * n + 255) / 256);
+    double *part = nullptr;
+    HIPCHK(hipMalloc(&part, 2 * nb * sizeof(double)));
+    hipLaunchKernelGGL(k_asym, dim3(nb), dim3(256), 0, st, P, n, ld, part);
+    std::vector<double> h(2 * nb);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(part);
+    if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("P check: ") + hipGetErrorString(e));
+    double asym = 0.0, mx = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        asym = std::max(asym, h[2 * b]);
+        mx = std::max(mx, h[2 * b + 1]);
+    }
+    if (!(asym <= 1e-12 * mx)) return fail(HFX_EASYM, "P is not symmetric within 1e-12 max|P|");
+    return HFX_OK;
+}
+
+const double *model_vrr();
+const double *model_post();
+double model_prim_overhead(int op, int L);
+
+// Launch the quartet kernels of every class pair; K must already be zero.
+hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, const hfx_opts *o,
+                          hipStream_t st, unsigned long long *count) {
+    const int op = kernel_op(o);
+    for (int cb = 0; cb < 6; ++cb)
+        for (int ck = 0; ck <= cb; ++ck) {
+            const ClassList &B = p->lists[cb], &Kl = p->lists[ck];
+            if (!B.n || !Kl.n) continue;
+            QuartetArgs a;
+            a.hdr = p->d_hdr;
+            a.prim = p->d_prim;
+            a.bra_ids = B.d_ids;
+            a.bra_Q = B.d_Q;
+            a.bra_grp = B.d_grp;
+            a.n_bra = B.n;
+            a.ket_ids = Kl.d_ids;
+            a.ket_Q = Kl.d_Q;
+            a.ket_goff = Kl.d_goff;
+            a.ket_gnp = Kl.d_gnp;
+            a.n_kgrp = Kl.ngrp;
+            a.same = (cb == ck);
+            a.tau = o->tau;
+            a.op = op;
+            a.om2 = op ? o->omega * o->omega : 0.0;
+            a.boys = p->d_boys;
+            a.P = P;
+            a.K = K;
+            a.ld = ld;
+            const int ci = cb * (cb + 1) / 2 + ck;
+            a.count = count ? count + 2 * ci : nullptr;
+            const int64_t nblk = (int64_t)B.n * Kl.ngrp;
+            if (nblk > INT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
+            k_eri_tab[ci](a, (unsigned)nblk, st);
+            HIPCHK(hipGetLastError());
+        }
+    return HFX_OK;
+}
+
+}  // namespace hfx
+
+extern "C" hfx_status hfx_schwarz_bounds(hfx_pairs p, const hfx_opts *o, double *q_host, void *stream) {
+    if (!p) return fail(HFX_EINVAL, "pairs is NULL");
+    hfx_status s = check_opts(o);
+    if (s != HFX_OK) return s;
+    s = compute_bounds(p, o, (hipStream_t)stream);
+    if (s != HFX_OK) return s;
+    if (q_host) std::memcpy(q_host, p->Q.data(), p->npair * sizeof(double));
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
+                                  const hfx_opts *o, void *stream, hfx_stats *st_out) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p) return fail(HFX_EINVAL, "pairs is NULL");
+    if (!P_dev || !K_dev) return fail(HFX_EINVAL, "P or K is NULL");
+    hfx_status s = check_opts(o);
+    if (s != HFX_OK) return s;
+    const int64_t n = p->nbf;
+    if (ld < n) return fail(HFX_EINVAL, "ld < n_bf");
+    if ((const double *)K_dev < P_dev + (n - 1) * ld + n && P_dev < (const double *)K_dev + (n - 1) * ld + n)
+        return fail(HFX_EINVAL, "K aliases P");
+    hipStream_t st = (hipStream_t)stream;
+    s = check_P(P_dev, n, ld, st);
+    if (s != HFX_OK) return s;
+    s = compute_bounds(p, o, st);
+    if (s != HFX_OK) return s;
+    s = build_lists(p, o->tau, st);
+    if (s != HFX_OK) return s;
+    if (!p->d_count) HIPCHK(hipMalloc(&p->d_count, 2 * HFX_NCLASS * sizeof(unsigned long long)));
+    unsigned long long *cnt = st_out ? p->d_count : nullptr;
+    if (cnt) hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, cnt, 2 * HFX_NCLASS);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, K_dev, n, ld);
+    HIPCHK(hipGetLastError());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st_out) {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, st));
+    }
+    s = launch_classes(p, P_dev, K_dev, ld, o, st, cnt);
+    if (s != HFX_OK) return s;
+    if (st_out) HIPCHK(hipEventRecord(e1, st));
+    const unsigned g = (unsigned)((n + 15) / 16);
+    hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(16, 16), 0, st, K_dev, n, ld);
+    HIPCHK(hipGetLastError());
+    if (st_out) {
+        std::vector<unsigned long long> h(2 * HFX_NCLASS);
+        HIPCHK(hipMemcpyAsync(h.data(), cnt, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        std::memset(st_out, 0, sizeof(*st_out));
+        st_out->device_s = ms * 1e-3;
+        const double *mv = model_vrr(), *mp = model_post();
+        for (int c = 0; c < HFX_NCLASS; ++c) {
+            int cb = 0;
+            while ((cb + 1) * (cb + 2) / 2 <= c) ++cb;
+            const int ck = c - cb * (cb + 1) / 2;
+            const int L = PAIR_L[cb][0] + PAIR_L[cb][1] + PAIR_L[ck][0] + PAIR_L[ck][1];
+            st_out->class_quartets[c] = (int64_t)h[2 * c];
+            st_out->quartets += (int64_t)h[2 * c];
+            st_out->prim_quartets += (int64_t)h[2 * c + 1];
+            st_out->flops += (mv[c] + model_prim_overhead(kernel_op(o), L)) * (double)h[2 * c + 1] +
+                             mp[c] * (double)h[2 * c];
+        }
+        st_out->latency_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_eval_quartets(hfx_pairs p, const hfx_opts *o, int64_t n, const int32_t *q,
+                                        double *out, void *stream) {
+    if (!p || !q || !out || n < 0) return fail(HFX_EINVAL, "bad arguments");
+    hfx_status s = check_opts(o);
+    if (s != HFX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int op = kernel_op(o);
+    const double om2 = op ? o->omega * o->omega : 0.0;
+    // bucket the quartets by class; canonical pair = (max, min) shell index
+    struct Item { int64_t idx; int32_t bra, ket; bool swp_bk; };
+    std::vector<std::vector<Item>> by(HFX_NCLASS);
+    std::vector<int64_t> outoff(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        int I = q[4 * i], J = q[4 * i + 1], Kk = q[4 * i + 2], L = q[4 * i + 3];
+        for (int x : {I, J, Kk, L})
+            if (x < 0 || x >= p->nshell) return fail(HFX_EINVAL, "shell index out of range");
+        const int64_t pb = (int64_t)std::max(I, J) * (std::max(I, J) + 1) / 2 + std::min(I, J);
+        const int64_t pk = (int64_t)std::max(Kk, L) * (std::max(Kk, L) + 1) / 2 + std::min(Kk, L);
+        int cb = p->pcls[pb], ck = p->pcls[pk];
+        Item it{i, (int32_t)pb, (int32_t)pk, false};
+        if (cb < ck) {
+            std::swap(it.bra, it.ket);
+            std::swap(cb, ck);
+            it.swp_bk = true;
+        }
+        by[cb * (cb + 1) / 2 + ck].push_back(it);
+        outoff[i + 1] = outoff[i] + (2 * p->sh[I].l + 1) * (2 * p->sh[J].l + 1) * (2 * p->sh[Kk].l + 1) *
+                                        (2 * p->sh[L].l + 1);
+    }
+    for (int c = 0; c < HFX_NCLASS; ++c) {
+        if (by[c].empty()) continue;
+        int cb = 0;
+        while ((cb + 1) * (cb + 2) / 2 <= c) ++cb;
+        const int ck = c - cb * (cb + 1) / 2;
+        const int na = 2 * PAIR_L[cb][0] + 1, nb = 2 * PAIR_L[cb][1] + 1, nc = 2 * PAIR_L[ck][0] + 1,
+                  nd = 2 * PAIR_L[ck][1] + 1;
+        const int nout = na * nb * nc * nd;
+        const int m = (int)by[c].size();
+        std::vector<int32_t> bk(2 * m);
+        for (int i = 0; i < m; ++i) {
+            bk[2 * i] = by[c][i].bra;
+            bk[2 * i + 1] = by[c][i].ket;
+        }
+        int32_t *d_bk = nullptr;
+        double *d_out = nullptr;
+        HIPCHK(hipMalloc(&d_bk, bk.size() * sizeof(int32_t)));
+        HIPCHK(hipMalloc(&d_out, (size_t)m * nout * sizeof(double)));
+        HIPCHK(hipMemcpyAsync(d_bk, bk.data(), bk.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        k_eval_tab[c](p->d_hdr, p->d_prim, d_bk, m, op, om2, p->d_boys, d_out, st);
+        std::vector<double> h((size_t)m * nout);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        hipFree(d_bk);
+        hipFree(d_out);
+        if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("eval: ") + hipGetErrorString(e));
+        // canonical block [A][B][C][D] -> caller order [I][J][K][L]
+        for (int i = 0; i < m; ++i) {
+            const Item &it = by[c][i];
+            const int64_t qi = it.idx;
+            int I = q[4 * qi], J = q[4 * qi + 1], Kk = q[4 * qi + 2], L = q[4 * qi + 3];
+            if (it.swp_bk) {
+                std::swap(I, Kk);
+                std::swap(J, L);
+            }
+            // canonical shells of bra: A = higher l (ties: larger index)
+            const PairHdr &hb = p->hdr_host[it.bra], &hk = p->hdr_host[it.ket];
+            const bool sab = (p->bfo[I] != hb.bfA);
+            const bool scd = (p->bfo[Kk] != hk.bfA);
+            const int nI = 2 * p->sh[I].l + 1, nJ = 2 * p->sh[J].l + 1, nK = 2 * p->sh[Kk].l + 1,
+                      nL = 2 * p->sh[L].l + 1;
+            double *dst = out + outoff[qi];
+            for (int a = 0; a < nI; ++a)
+                for (int b = 0; b < nJ; ++b)
+                    for (int cc = 0; cc < nK; ++cc)
+                        for (int d = 0; d < nL; ++d) {
+                            const int A = sab ? b : a, B = sab ? a : b, C = scd ? d : cc, D = scd ? cc : d;
+                            const double v = h[(size_t)i * nout + ((A * nb + B) * nc + C) * nd + D];
+                            if (!it.swp_bk)
+                                dst[((a * nJ + b) * nK + cc) * nL + d] = v;
+                            else  // caller's (I J) is our ket: output index order is (K L I J) of ours
+                                dst[((cc * nL + d) * nI + a) * nJ + b] = v;
+                        }
+        }
+    }
+    return HFX_OK;
+}

@@ -1,0 +1,53 @@
+// Host-side state of a pair handle (device pair data, bounds, screening lists).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "hfx.h"
+#include "hfx_device.hpp"
+
+namespace hfx {
+
+struct ClassList {
+    int n = 0, ngrp = 0;
+    int32_t *d_ids = nullptr, *d_grp = nullptr, *d_goff = nullptr, *d_gnp = nullptr;
+    double *d_Q = nullptr;
+    std::vector<int> goff, gnp;
+    std::vector<int32_t> h_ids, h_grp;
+    std::vector<double> h_Q;
+};
+
+hfx_status fail(hfx_status s, const std::string &msg);
+int kernel_op(const hfx_opts *o);
+extern const int PAIR_L[6][2];
+
+}  // namespace hfx
+
+struct hfx_pairs_s {
+    int natom = 0, nshell = 0;
+    int64_t nbf = 0, npair = 0, nrec = 0, dev_bytes = 0;
+    hipStream_t stream = nullptr;
+    std::vector<hfx_shell> sh;
+    std::vector<double> xyz, exps, cn;
+    std::vector<int> bfo;
+    std::vector<int8_t> pcls;
+    std::vector<int32_t> class_ids[6];
+    std::vector<hfx::PairHdr> hdr_host;
+    hfx::PairHdr *d_hdr = nullptr;
+    hfx::PrimRec *d_prim = nullptr;
+    double *d_Q = nullptr;
+    const double *d_boys = nullptr;
+    unsigned long long *d_count = nullptr;
+    bool have_Q = false;
+    int q_op = -1;
+    double q_om2 = -1.0;
+    std::vector<double> Q;
+    double qmax = 0.0;
+    bool lists_valid = false;
+    double list_tau = -1.0;
+    hfx::ClassList lists[6];
+    void drop_lists();
+    ~hfx_pairs_s();
+};

@@ -1,0 +1,207 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: squared Schwarz factors (diagonal integrals) to 1e-13 of the largest,
+raw integrals to 1e-12 of the quartet's Schwarz bound Q_IJ Q_KL, plain FP64 K
+within 1e-10 hartree max-abs (the target accuracy of the FP64 build).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import hfx_inputs as hi
+import oracle
+import paper_2009_03559_amd as hfx
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+
+
+def _gpu_K(s, tau, omega, stats=False):
+    p = hfx.pairs_from_system(s, hfx.opts(tau=tau, omega=omega))
+    P = torch.from_numpy(s.P).cuda()
+    K = torch.empty_like(P)
+    st = hfx.build_K(p, P, K, hfx.opts(tau=tau, omega=omega), stats=stats)
+    torch.cuda.synchronize()
+    return K.cpu().numpy(), st, p
+
+
+def _pid(i, j):
+    i, j = max(i, j), min(i, j)
+    return i * (i + 1) // 2 + j
+
+
+def _spd_small(seed=21, natom=3, nprim=(1, 3)):
+    return hi.lattice_system(natom, seed=seed, nprim_range=nprim)
+
+
+@pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
+def test_schwarz_factors(omega):
+    for s in (hi.config0(), _spd_small()):
+        _say("schwarz", s.meta["name"], omega)
+        p = hfx.pairs_from_system(s)
+        q = hfx.schwarz_bounds(p, hfx.opts(omega=omega))
+        qo = oracle.schwarz(s, omega=omega)
+        # the bounds are square roots of diagonal integrals: compare those on an
+        # absolute scale (a small diagonal value carries the rounding of its
+        # larger contributions)
+        err = np.abs(q ** 2 - qo ** 2).max()
+        assert err <= 1e-13 * (qo ** 2).max(), err
+
+
+@pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
+def test_raw_integrals_every_class(omega):
+    """Every one of the 21 classes, both orders inside pairs and across."""
+    s = _spd_small(seed=22, natom=2, nprim=(2, 3))
+    p = hfx.pairs_from_system(s)
+    rng = np.random.default_rng(5)
+    quartets = []
+    for I in range(s.nshell):
+        for J in range(s.nshell):
+            for K in range(s.nshell):
+                for L in range(s.nshell):
+                    if rng.random() < 0.02:
+                        quartets.append((I, J, K, L))
+    _say("eval", len(quartets), "quartets")
+    got = hfx.eval_quartets(p, hfx.opts(omega=omega), quartets, s.shell_l)
+    Q = oracle.schwarz(s, omega=omega)
+    seen = set()
+    for q, g in zip(quartets, got):
+        ref = oracle.shell_quartet(s, *q, omega=omega)
+        # rounding scale of a quartet: its Schwarz bound Q_IJ Q_KL
+        bound = Q[_pid(q[0], q[1])] * Q[_pid(q[2], q[3])]
+        assert np.abs(g - ref).max() <= 1e-12 * bound, (q, np.abs(g - ref).max(), bound)
+        ls = sorted([tuple(sorted((s.shell_l[q[0]], s.shell_l[q[1]]), reverse=True)),
+                     tuple(sorted((s.shell_l[q[2]], s.shell_l[q[3]]), reverse=True))], reverse=True)
+        seen.add(tuple(ls))
+    assert len(seen) == 21, len(seen)
+
+
+@pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
+def test_K_config0(omega):
+    s = hi.config0()
+    _say("K config0", omega)
+    Ko, _, cnt = oracle.build_K(s, tau=1e-10, omega=omega)
+    Kg, st, _ = _gpu_K(s, 1e-10, omega, stats=True)
+    assert np.abs(Kg - Ko).max() <= 1e-10
+    assert np.abs(Kg - Kg.T).max() == 0.0
+    assert st["quartets"] == cnt["quartets"]
+    assert st["prim_quartets"] == cnt["prim_quartets"]
+    assert abs(np.trace(s.P @ Kg) - np.trace(s.P @ Ko)) <= 1e-10 * abs(np.trace(s.P @ Ko))
+
+
+@pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
+@pytest.mark.parametrize("tau", [0.0, 1e-10, 1e-6])
+def test_K_dzp_small(omega, tau):
+    """s, p and d shells; ket ranges longer than one 64-lane chunk with a
+    ragged tail; tau = 0 (every quartet), tight and loose screening."""
+    s = _spd_small(seed=23, natom=8, nprim=(1, 3))
+    _say("K dzp8", omega, tau)
+    Ko, _, cnt = oracle.build_K(s, tau=tau, omega=omega)
+    Kg, st, _ = _gpu_K(s, tau, omega, stats=True)
+    assert np.abs(Kg - Ko).max() <= 1e-10, np.abs(Kg - Ko).max()
+    assert st["quartets"] == cnt["quartets"]
+    assert list(st["class_quartets"]) == list(cnt["per_class"])
+
+
+def test_K_degenerate_single_shell_and_s_only():
+    # one atom with one s shell: the only quartet is (II|II), degeneracy 1/8
+    s = hi.tiny_sp_cluster(seed=3, natom=1, ls=(0,), nprim=2)
+    Ko, _, _ = oracle.build_K(s, tau=0.0, omega=0.11)
+    Kg, _, _ = _gpu_K(s, 0.0, 0.11)
+    assert np.abs(Kg - Ko).max() <= 1e-13
+    # s-only cluster
+    s = hi.tiny_sp_cluster(seed=4, natom=6, ls=(0,), nprim=3)
+    Ko, _, _ = oracle.build_K(s, tau=1e-10, omega=0.0)
+    Kg, _, _ = _gpu_K(s, 1e-10, 0.0)
+    assert np.abs(Kg - Ko).max() <= 1e-12
+
+
+def test_K_everything_screened_is_zero():
+    s = hi.config0()
+    Kg, st, _ = _gpu_K(s, 1e6, 0.0, stats=True)
+    assert st["quartets"] == 0
+    assert not Kg.any()
+
+
+def test_K_asymmetric_P_rejected():
+    s = hi.config0()
+    p = hfx.pairs_from_system(s)
+    P = torch.from_numpy(s.P).cuda()
+    P[0, 1] += 1e-3
+    K = torch.empty_like(P)
+    with pytest.raises(hfx.HfxError) as e:
+        hfx.build_K(p, P, K, hfx.opts())
+    assert e.value.status == hfx.HFX_EASYM
+
+
+def test_K_leading_dimension():
+    s = hi.config0()
+    n = s.nbf
+    big = torch.zeros((n, n + 7), dtype=torch.float64, device="cuda")
+    big[:, :n] = torch.from_numpy(s.P).cuda()
+    Kb = torch.full((n, n + 7), 7.0, dtype=torch.float64, device="cuda")
+    p = hfx.pairs_from_system(s)
+    hfx.build_K(p, big[:, :n], Kb[:, :n], hfx.opts(omega=0.11))
+    torch.cuda.synchronize()
+    Ko, _, _ = oracle.build_K(s, tau=1e-10, omega=0.11)
+    Kg = Kb.cpu().numpy()
+    assert np.abs(Kg[:, :n] - Ko).max() <= 1e-10
+    assert (Kg[:, n:] == 7.0).all()
+
+
+def test_repeat_build_reuses_lists_and_is_stable():
+    s = _spd_small(seed=24, natom=5, nprim=(2, 3))
+    p = hfx.pairs_from_system(s)
+    P = torch.from_numpy(s.P).cuda()
+    K1 = torch.empty_like(P)
+    K2 = torch.empty_like(P)
+    o = hfx.opts(tau=1e-10, omega=0.11)
+    hfx.build_K(p, P, K1, o)
+    hfx.build_K(p, P * 2.0, K2, o)
+    torch.cuda.synchronize()
+    assert torch.allclose(K2, 2.0 * K1, rtol=1e-12, atol=1e-14)
+
+
+def test_full_size_config1_sampled():
+    """configs-1 system at full size (1280 shells): all 819,840 Schwarz factors
+    on the GPU; a sample of them and of raw quartet integrals (every class)
+    against the oracle one by one."""
+    s = hi.config1()
+    _say("config1 pairs")
+    p = hfx.pairs_from_system(s)
+    q = hfx.schwarz_bounds(p, hfx.opts(omega=hi.OMEGA_HSE))
+    assert q.shape == (1280 * 1281 // 2,)
+    rng = np.random.default_rng(9)
+    idx = rng.choice(len(q), 300, replace=False)
+    for pid in idx:
+        I = int((np.sqrt(8 * pid + 1) - 1) // 2)
+        while I * (I + 1) // 2 > pid:
+            I -= 1
+        while (I + 1) * (I + 2) // 2 <= pid:
+            I += 1
+        J = pid - I * (I + 1) // 2
+        blk = oracle.shell_quartet(s, I, J, I, J, omega=hi.OMEGA_HSE)
+        ni, nj = blk.shape[:2]
+        qo = np.sqrt(max(blk[i, j, i, j] for i in range(ni) for j in range(nj)))
+        assert abs(q[pid] ** 2 - qo ** 2) <= 1e-13 * max(qo ** 2, 1e-3)
+    quartets = rng.integers(0, s.nshell, size=(400, 4))
+    got = hfx.eval_quartets(p, hfx.opts(omega=hi.OMEGA_HSE), quartets, s.shell_l)
+    for qq, g in zip(quartets, got):
+        ref = oracle.shell_quartet(s, *qq, omega=hi.OMEGA_HSE)
+        bound = q[_pid(qq[0], qq[1])] * q[_pid(qq[2], qq[3])]
+        assert np.abs(g - ref).max() <= 1e-12 * bound + 1e-300
