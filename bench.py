@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark of the screened exchange build on one MI355X.
+
+Workload: the 256-atom DZP-like lattice system (1280 shells, 3328 spherical
+functions; erfc(omega r)/r with omega = 0.11; Schwarz tau = 1e-10; plain
+FP64).  A full K-build of it is ~10^13 primitive quartets -- far more than a
+one-minute timed region -- so one step is one GPU's share of that build when
+it is distributed over `--shards` devices (bra pairs of every class dealt
+round-robin, `hfx_build_K_shard`): the kernels run at the workload's real
+shape and class mix, and `projected_full_build_s` states shards x step time.
+
+A step = one pass of the whole path on that share: the P symmetry check, the
+Schwarz bounds and screening lists (cached in the pair handle after the first
+call, as across SCF iterations), all 21 class kernels and the
+symmetrisation.  Pair data and P are resident in HBM before timing starts.
+
+Output: one JSON line (rank 0) with the metric, a roofline object for the
+dominant class kernel (device time from HIP events on the launch stream) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shards", type=int, default=64,
+                    help="the step is one of this many bra-pair shards of the full build")
+    ap.add_argument("--shard", type=int, default=0)
+    ap.add_argument("--natom", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle timing leg")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(sysm, tau, omega, budget_s):
+    """The oracle on a seeded sample of screened quartets of the same
+    workload, on all host cores: a random pool of shell pairs, their Schwarz
+    factors from the oracle itself, every unique quartet of the pool that
+    passes Q_IJ Q_KL >= tau, shuffled; the sample size is calibrated to the
+    time budget."""
+    import oracle
+
+    rng = np.random.default_rng(12345)
+    npair = sysm.nshell * (sysm.nshell + 1) // 2
+    cores = len(os.sched_getaffinity(0))
+    pool = np.unique(rng.integers(0, npair, size=min(npair, 700)))
+    qpool = oracle.schwarz_list(sysm, pool, omega=omega)
+    ii, jj = np.tril_indices(len(pool))
+    keep = qpool[ii] * qpool[jj] >= tau
+    cand = np.stack([pool[ii[keep]], pool[jj[keep]]], axis=1)
+    rng.shuffle(cand)
+    probe = cand[:256]
+    t0 = time.perf_counter()
+    oracle.digest_list(sysm, probe, omega=omega, nthreads=cores)
+    dt = time.perf_counter() - t0
+    n = int(max(256, min(len(cand), 256 * budget_s / max(dt, 1e-3))))
+    sample = cand[:n]
+    t0 = time.perf_counter()
+    oracle.digest_list(sysm, sample, omega=omega, nthreads=cores)
+    dt = time.perf_counter() - t0
+    desc = (f"{n} screened unique shell quartets (Q_IJ Q_KL >= tau by the oracle's own Schwarz factors) "
+            f"among a seeded random pool of {len(pool)} shell pairs of the same system; FP64 integrals and "
+            f"digestion into K; {dt:.1f} s")
+    return {"value": n / dt, "unit": "quartets/s", "cores": cores, "kind": "oracle", "sample": desc}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported in this build "
+              "(the multi-GPU split is hfx_build_K_shard + one all-reduce of K)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import hfx_inputs as hi
+    import paper_2009_03559_amd as hfx
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    tau, omega = 1e-10, hi.OMEGA_HSE
+    sysm = hi.config1() if a.natom == 256 else hi.lattice_system(a.natom, seed=1, name=f"lattice_dzp{a.natom}")
+    o = hfx.opts(tau=tau, omega=omega)
+    pairs = hfx.pairs_from_system(sysm, o)
+    P = torch.from_numpy(sysm.P).to(dev)
+    K = torch.empty_like(P)
+    # bounds and lists are built once and stay resident (SCF-like reuse)
+    hfx.schwarz_bounds(pairs, o)
+    print(f"# workload {sysm.meta['name']}: {sysm.natom} atoms, {sysm.nshell} shells, {sysm.nbf} functions; "
+          f"shard {a.shard}/{a.shards}", file=sys.stderr, flush=True)
+    for w in range(a.warmup):
+        hfx.build_K_shard(pairs, P, K, o, a.shard, a.shards)
+        torch.cuda.synchronize()
+        print(f"# warmup {w} done", file=sys.stderr, flush=True)
+    times, stats = [], []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for k in range(a.steps):
+        t0 = time.perf_counter()
+        st = hfx.build_K_shard(pairs, P, K, o, a.shard, a.shards, stats=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        stats.append(st)
+        print(f"# step {k}: {times[-1]:.3f} s, {st['quartets']} quartets", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    Kh = K.cpu().numpy()
+    assert np.isfinite(Kh).all() and np.abs(Kh - Kh.T).max() == 0.0
+    st = stats[-1]
+    q_per_step = st["quartets"]
+    ms = 1e3 * total / a.steps
+    value = q_per_step * a.steps / total
+    # roofline of the dominant class kernel (largest device time)
+    ci = int(np.argmax(st["class_device_s"]))
+    cls_t = np.mean([s["class_device_s"][ci] for s in stats])
+    ach = st["class_flops"][ci] / cls_t / 1e12
+    dev_s = np.mean([s["device_s"] for s in stats])
+    out = {
+        "metric": "HFX K-build screened ERI quartets/s",
+        "value": value,
+        "unit": "quartets/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{sysm.meta['name']}: {sysm.natom}-atom DZP-like lattice (2s2p1d, 3-6 primitives), "
+                        f"{sysm.nshell} shells, {sysm.nbf} functions, erfc omega={omega}, tau={tau}; "
+                        f"step = shard {a.shard} of {a.shards} round-robin bra-pair shards of the full K-build",
+            "shards": a.shards,
+            "precision": "fp64",
+        },
+        "gflops": st["flops"] / dev_s / 1e9,
+        "frac_fp64_vector_peak": st["flops"] / dev_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+        "p50_ms": float(np.percentile(times, 50) * 1e3),
+        "p99_ms": float(np.percentile(times, 99) * 1e3),
+        "quartets_per_step": q_per_step,
+        "prim_quartets_per_step": st["prim_quartets"],
+        "projected_full_build_s": dev_s * a.shards,
+        "class_quartets": dict(zip(hfx.CLASS_NAMES, st["class_quartets"])),
+        "class_ms": dict(zip(hfx.CLASS_NAMES, [round(1e3 * x, 3) for x in st["class_device_s"]])),
+        "roofline": {
+            "bound": "alu",
+            "kernel": f"k_eri<Eri{hfx.CLASS_TAGS[ci]}> {hfx.CLASS_NAMES[ci]}",
+            "achieved": ach,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+        },
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sysm, tau, omega, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -103,6 +103,8 @@ typedef struct {
     int64_t prim_quartets; /* primitive quartets evaluated */
     double flops;          /* algorithmic FLOPs (model, FMA = 2) */
     int64_t class_quartets[HFX_NCLASS];
+    double class_device_s[HFX_NCLASS]; /* device time of each class kernel */
+    double class_flops[HFX_NCLASS];    /* algorithmic FLOPs of each class */
 } hfx_stats;
 
 /* Validate and normalise the basis, enumerate all shell pairs I >= J (A =
@@ -134,6 +136,19 @@ hfx_status hfx_schwarz_bounds(hfx_pairs p, const hfx_opts *o, double *q_host_or_
  * n_bf, tau < 0, omega < 0, aliasing), EASYM, ENOMEM, EDEVICE. */
 hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
                        const hfx_opts *o, void *stream, hfx_stats *st_or_null);
+
+/* One device's share of the exchange build when it is distributed over
+ * nshards devices: the bra pairs of every class (slots of the Q-sorted
+ * lists) are dealt round-robin, slot s going to shard s mod nshards, and
+ * this call digests the quartets of shard `shard` only.  K receives that
+ * share's symmetrised partial K; the sum over all shards is the K of
+ * hfx_build_K (the cross-device step is then one all-reduce of K).  The
+ * round-robin deal balances cost the way the quartet-level distribution of
+ * Sec. 3.1 does, without replicated screening.  nshards = 1 is hfx_build_K.
+ * Errors: as hfx_build_K, EINVAL if shard is not in [0, nshards). */
+hfx_status hfx_build_K_shard(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
+                             const hfx_opts *o, int32_t shard, int32_t nshards, void *stream,
+                             hfx_stats *st_or_null);
 
 /* Many independent systems in one persistent launch per pass, fed by a
  * device work queue (Sec. 5 proposes dynamic distribution of the quartet

@@ -50,6 +50,8 @@ def lib():
         L.oracle_eri_tensor.argtypes = basis + [ctypes.c_double, _f64p]
         L.oracle_schwarz.restype = ctypes.c_int
         L.oracle_schwarz.argtypes = basis + [ctypes.c_double, _f64p]
+        L.oracle_schwarz_list.restype = ctypes.c_int
+        L.oracle_schwarz_list.argtypes = basis + [ctypes.c_double, ctypes.c_int64, _i64p, _f64p]
         L.oracle_build_K.restype = ctypes.c_int
         L.oracle_build_K.argtypes = basis + [_f64p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                              _f64p, _f64p, _i64p]
@@ -108,6 +110,16 @@ def schwarz(sys, omega=0.0) -> np.ndarray:
     rc = lib().oracle_schwarz(*_basis_args(sys), float(omega), Q)
     if rc:
         raise ValueError("oracle_schwarz: invalid basis")
+    return Q
+
+
+def schwarz_list(sys, pids, omega=0.0) -> np.ndarray:
+    """Schwarz factors of the listed pair indices p = I(I+1)/2 + J."""
+    pids = np.ascontiguousarray(pids, dtype=np.int64)
+    Q = np.zeros(len(pids), dtype=np.float64)
+    rc = lib().oracle_schwarz_list(*_basis_args(sys), float(omega), len(pids), pids, Q)
+    if rc:
+        raise ValueError("oracle_schwarz_list: invalid basis")
     return Q
 
 

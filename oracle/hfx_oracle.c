@@ -457,6 +457,39 @@ int oracle_schwarz(const double *xyz, int nshell, const int32_t *atom, const int
     return 0;
 }
 
+/* Schwarz factors of an explicit list of pair indices (same definition). */
+int oracle_schwarz_list(const double *xyz, int nshell, const int32_t *atom, const int32_t *l,
+                        const int32_t *nprim, const int32_t *off, const double *exps,
+                        const double *coefs, double omega, int64_t n, const int64_t *pids, double *Q) {
+    basis_t B; double *cn;
+    if (setup_basis(&B, xyz, nshell, atom, l, nprim, off, exps, coefs, &cn)) return 1;
+    #pragma omp parallel
+    {
+        vtab_t *W = malloc(sizeof(vtab_t));
+        double blk[625];
+        #pragma omp for schedule(dynamic, 4)
+        for (int64_t x = 0; x < n; x++) {
+            int64_t p = pids[x];
+            int I = (int)((sqrt(8.0 * p + 1) - 1) / 2);
+            while ((int64_t)I * (I + 1) / 2 > p) I--;
+            while ((int64_t)(I + 1) * (I + 2) / 2 <= p) I++;
+            int J = (int)(p - (int64_t)I * (I + 1) / 2);
+            shell_quartet(&B, I, J, I, J, omega, W, blk);
+            int ni = nsph(l[I]), nj = nsph(l[J]);
+            double mx = 0;
+            for (int i = 0; i < ni; i++)
+                for (int j = 0; j < nj; j++) {
+                    double v = blk[((i * nj + j) * ni + i) * nj + j];
+                    if (v > mx) mx = v;
+                }
+            Q[x] = sqrt(mx);
+        }
+        free(W);
+    }
+    free(cn);
+    return 0;
+}
+
 /* Digest one unique shell quartet (IJ|KL) into K' (n x n, row-major):
  * with degeneracy d = (1/2 if I=J)(1/2 if K=L)(1/2 if IJ=KL) and value v of
  * function quartet (ijkl):

@@ -22,9 +22,11 @@ PREC_FP64, PREC_MIXED = 0, 1
 NCLASS = 21
 PAIR_CLASSES = ["ss", "ps", "pp", "ds", "dp", "dd"]
 CLASS_NAMES = [f"({PAIR_CLASSES[b]}|{PAIR_CLASSES[k]})" for b in range(6) for k in range(b + 1)]
+_PAIR_L = ["00", "10", "11", "20", "21", "22"]
+CLASS_TAGS = [_PAIR_L[b] + _PAIR_L[k] for b in range(6) for k in range(b + 1)]
 
 # Symbols declared in include/hfx.h.
-EXPORTS = ["hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_K_batch",
+EXPORTS = ["hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_K_shard", "hfx_build_K_batch",
            "hfx_server_create", "hfx_submit", "hfx_poll", "hfx_pairs_nbf", "hfx_pairs_npair",
            "hfx_pairs_device_bytes", "hfx_eval_quartets", "hfx_pairs_destroy", "hfx_server_destroy",
            "hfx_last_error"]
@@ -50,12 +52,14 @@ class Opts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("latency_s", ctypes.c_double), ("device_s", ctypes.c_double), ("quartets", ctypes.c_int64),
                 ("quartets_fp32", ctypes.c_int64), ("prim_quartets", ctypes.c_int64), ("flops", ctypes.c_double),
-                ("class_quartets", ctypes.c_int64 * NCLASS)]
+                ("class_quartets", ctypes.c_int64 * NCLASS), ("class_device_s", ctypes.c_double * NCLASS),
+                ("class_flops", ctypes.c_double * NCLASS)]
 
     def as_dict(self):
         return dict(latency_s=self.latency_s, device_s=self.device_s, quartets=self.quartets,
                     quartets_fp32=self.quartets_fp32, prim_quartets=self.prim_quartets, flops=self.flops,
-                    class_quartets=list(self.class_quartets))
+                    class_quartets=list(self.class_quartets), class_device_s=list(self.class_device_s),
+                    class_flops=list(self.class_flops))
 
 
 _lib = None
@@ -74,6 +78,8 @@ def lib():
                                             ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
         L.hfx_schwarz_bounds.argtypes = [vp, ctypes.POINTER(Opts), vp, vp]
         L.hfx_build_K.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(Opts), vp, ctypes.POINTER(Stats)]
+        L.hfx_build_K_shard.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(Opts), ctypes.c_int32,
+                                        ctypes.c_int32, vp, ctypes.POINTER(Stats)]
         L.hfx_build_K_batch.argtypes = [ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp,
                                         ctypes.POINTER(Stats)]
         L.hfx_server_create.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(vp)]
@@ -87,7 +93,7 @@ def lib():
         L.hfx_pairs_destroy.restype = None
         L.hfx_server_destroy.argtypes = [vp]
         L.hfx_server_destroy.restype = None
-        for f in ("hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_K_batch",
+        for f in ("hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_K_shard", "hfx_build_K_batch",
                   "hfx_server_create", "hfx_submit", "hfx_poll", "hfx_eval_quartets"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -176,6 +182,15 @@ def build_K(p: Pairs, P, K, o: Opts, stream=None, stats=False):
     st = Stats() if stats else None
     _check(lib().hfx_build_K(p.handle, _ptr(P), _ptr(K), ld, ctypes.byref(o), _stream_ptr(stream),
                              ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def build_K_shard(p: Pairs, P, K, o: Opts, shard: int, nshards: int, stream=None, stats=False):
+    """One shard's symmetrised partial K (the K of hfx_build_K summed over shards)."""
+    ld = int(P.stride(0))
+    st = Stats() if stats else None
+    _check(lib().hfx_build_K_shard(p.handle, _ptr(P), _ptr(K), ld, ctypes.byref(o), int(shard), int(nshards),
+                                   _stream_ptr(stream), ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
 
 

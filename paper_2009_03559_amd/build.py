@@ -35,6 +35,7 @@ def _compile(src: str) -> str:
 
 
 def build(jobs: int | None = None, verbose: bool = True) -> str:
+    """Generate, compile and link; returns the library path."""
     os.makedirs(GEN, exist_ok=True)
     os.makedirs(OBJ, exist_ok=True)
     subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_eri.py"), "--outdir", GEN,

@@ -188,6 +188,8 @@ struct QuartetArgs {
     const double *bra_Q;
     const int32_t *bra_grp;   // group index of each bra slot
     int32_t n_bra;
+    int32_t bra_first;        // slots bra_first, bra_first + bra_stride, ... (sharding)
+    int32_t bra_stride;
     const int32_t *ket_ids;   // ket class, same order
     const double *ket_Q;
     const int32_t *ket_goff;  // n_kgrp + 1 group offsets into the ket list
@@ -228,8 +230,9 @@ __device__ __forceinline__ int ket_cut(const QuartetArgs &a, int p, int g, int *
 // 64 lanes walk the screened ket range; bra primitive data is uniform.
 template <class C>
 __global__ __launch_bounds__(64) void k_eri(QuartetArgs a) {
-    const int p = blockIdx.x / a.n_kgrp;
-    const int g = blockIdx.x - p * a.n_kgrp;
+    const int j = blockIdx.x / a.n_kgrp;
+    const int g = blockIdx.x - j * a.n_kgrp;
+    const int p = a.bra_first + j * a.bra_stride;
     if (p >= a.n_bra) return;
     int lo = 0;
     const int cut = ket_cut(a, p, g, &lo);

@@ -541,12 +541,15 @@ double model_prim_overhead(int op, int L);
 
 // Launch the quartet kernels of every class pair; K must already be zero.
 hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, const hfx_opts *o,
-                          hipStream_t st, unsigned long long *count) {
+                          hipStream_t st, unsigned long long *count, int shard, int nshards,
+                          hipEvent_t *ev) {
     const int op = kernel_op(o);
     for (int cb = 0; cb < 6; ++cb)
         for (int ck = 0; ck <= cb; ++ck) {
             const ClassList &B = p->lists[cb], &Kl = p->lists[ck];
-            if (!B.n || !Kl.n) continue;
+            const int ci = cb * (cb + 1) / 2 + ck;
+            if (ev) HIPCHK(hipEventRecord(ev[ci], st));
+            if (!B.n || !Kl.n || shard >= B.n) continue;
             QuartetArgs a;
             a.hdr = p->d_hdr;
             a.prim = p->d_prim;
@@ -554,6 +557,8 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             a.bra_Q = B.d_Q;
             a.bra_grp = B.d_grp;
             a.n_bra = B.n;
+            a.bra_first = shard;
+            a.bra_stride = nshards;
             a.ket_ids = Kl.d_ids;
             a.ket_Q = Kl.d_Q;
             a.ket_goff = Kl.d_goff;
@@ -567,13 +572,13 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             a.P = P;
             a.K = K;
             a.ld = ld;
-            const int ci = cb * (cb + 1) / 2 + ck;
             a.count = count ? count + 2 * ci : nullptr;
-            const int64_t nblk = (int64_t)B.n * Kl.ngrp;
+            const int64_t nblk = (int64_t)((B.n - shard + nshards - 1) / nshards) * Kl.ngrp;
             if (nblk > INT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
             k_eri_tab[ci](a, (unsigned)nblk, st);
             HIPCHK(hipGetLastError());
         }
+    if (ev) HIPCHK(hipEventRecord(ev[HFX_NCLASS], st));
     return HFX_OK;
 }
 
@@ -589,11 +594,12 @@ extern "C" hfx_status hfx_schwarz_bounds(hfx_pairs p, const hfx_opts *o, double 
     return HFX_OK;
 }
 
-extern "C" hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
-                                  const hfx_opts *o, void *stream, hfx_stats *st_out) {
+static hfx_status build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
+                               const hfx_opts *o, int shard, int nshards, void *stream, hfx_stats *st_out) {
     auto t0 = std::chrono::steady_clock::now();
     if (!p) return fail(HFX_EINVAL, "pairs is NULL");
     if (!P_dev || !K_dev) return fail(HFX_EINVAL, "P or K is NULL");
+    if (nshards < 1 || shard < 0 || shard >= nshards) return fail(HFX_EINVAL, "shard not in [0, nshards)");
     hfx_status s = check_opts(o);
     if (s != HFX_OK) return s;
     const int64_t n = p->nbf;
@@ -612,15 +618,11 @@ extern "C" hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_de
     if (cnt) hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, cnt, 2 * HFX_NCLASS);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, K_dev, n, ld);
     HIPCHK(hipGetLastError());
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (st_out) {
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
-        HIPCHK(hipEventRecord(e0, st));
-    }
-    s = launch_classes(p, P_dev, K_dev, ld, o, st, cnt);
+    hipEvent_t ev[HFX_NCLASS + 1] = {};
+    if (st_out)
+        for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    s = launch_classes(p, P_dev, K_dev, ld, o, st, cnt, shard, nshards, st_out ? ev : nullptr);
     if (s != HFX_OK) return s;
-    if (st_out) HIPCHK(hipEventRecord(e1, st));
     const unsigned g = (unsigned)((n + 15) / 16);
     hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(16, 16), 0, st, K_dev, n, ld);
     HIPCHK(hipGetLastError());
@@ -628,11 +630,9 @@ extern "C" hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_de
         std::vector<unsigned long long> h(2 * HFX_NCLASS);
         HIPCHK(hipMemcpyAsync(h.data(), cnt, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
         std::memset(st_out, 0, sizeof(*st_out));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[HFX_NCLASS]));
         st_out->device_s = ms * 1e-3;
         const double *mv = model_vrr(), *mp = model_post();
         for (int c = 0; c < HFX_NCLASS; ++c) {
@@ -640,15 +640,31 @@ extern "C" hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_de
             while ((cb + 1) * (cb + 2) / 2 <= c) ++cb;
             const int ck = c - cb * (cb + 1) / 2;
             const int L = PAIR_L[cb][0] + PAIR_L[cb][1] + PAIR_L[ck][0] + PAIR_L[ck][1];
+            float cm = 0.f;
+            HIPCHK(hipEventElapsedTime(&cm, ev[c], ev[c + 1]));
+            st_out->class_device_s[c] = cm * 1e-3;
             st_out->class_quartets[c] = (int64_t)h[2 * c];
+            st_out->class_flops[c] = (mv[c] + model_prim_overhead(kernel_op(o), L)) * (double)h[2 * c + 1] +
+                                     mp[c] * (double)h[2 * c];
             st_out->quartets += (int64_t)h[2 * c];
             st_out->prim_quartets += (int64_t)h[2 * c + 1];
-            st_out->flops += (mv[c] + model_prim_overhead(kernel_op(o), L)) * (double)h[2 * c + 1] +
-                             mp[c] * (double)h[2 * c];
+            st_out->flops += st_out->class_flops[c];
         }
+        for (auto &e : ev) hipEventDestroy(e);
         st_out->latency_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return HFX_OK;
+}
+
+extern "C" hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
+                                  const hfx_opts *o, void *stream, hfx_stats *st_out) {
+    return build_K_impl(p, P_dev, K_dev, ld, o, 0, 1, stream, st_out);
+}
+
+extern "C" hfx_status hfx_build_K_shard(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
+                                        const hfx_opts *o, int32_t shard, int32_t nshards, void *stream,
+                                        hfx_stats *st_out) {
+    return build_K_impl(p, P_dev, K_dev, ld, o, shard, nshards, stream, st_out);
 }
 
 extern "C" hfx_status hfx_eval_quartets(hfx_pairs p, const hfx_opts *o, int64_t n, const int32_t *q,
