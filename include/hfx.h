@@ -75,8 +75,12 @@ typedef struct {
  * synthetic workloads 1e-10).  op/omega: kernel; ERFC with omega == 0 is
  * the Coulomb kernel.  prec: FP64, or MIXED, where quartets whose bound
  * Q_IJ Q_KL is below mixed_cut are evaluated in FP32 (FP64 large-T Boys,
- * FP64 bounds and FP64 accumulation into K).  prim_tau: reserved, must be 0.
- * flags: reserved, must be 0. */
+ * FP64 bounds and FP64 accumulation into K).  prim_tau (>= 0): inside a
+ * computed quartet, primitive quartets whose bound B_ab B_cd is below
+ * prim_tau may be skipped, where B_ab is the Schwarz factor of the single
+ * primitive pair (a bound on every primitive contribution); 0 keeps every
+ * primitive quartet (exact evaluation of each computed quartet).  flags:
+ * reserved, must be 0. */
 typedef struct {
     double tau;
     int32_t op;

@@ -105,11 +105,17 @@ def _check(rc):
         raise HfxError(rc, lib().hfx_last_error().decode())
 
 
-def opts(tau=1e-10, omega=0.0, prec=PREC_FP64, mixed_cut=1e-5, op=None) -> Opts:
+PRIM_TAU_REL = 1e-6  # default primitive-quartet threshold relative to tau
+
+
+def opts(tau=1e-10, omega=0.0, prec=PREC_FP64, mixed_cut=1e-5, op=None, prim_tau=None) -> Opts:
+    """Options; prim_tau defaults to 1e-6 tau (0 = every primitive quartet)."""
     if op is None:
         op = OP_ERFC if omega > 0 else OP_COULOMB
+    if prim_tau is None:
+        prim_tau = PRIM_TAU_REL * tau
     return Opts(tau=float(tau), op=int(op), omega=float(omega), prec=int(prec), mixed_cut=float(mixed_cut),
-                prim_tau=0.0, flags=0)
+                prim_tau=float(prim_tau), flags=0)
 
 
 def _stream_ptr(stream):

@@ -329,6 +329,143 @@ def emit_post(em, la, lb, lc, ld, name="post"):
     return flops
 
 
+def emit_digest_part(em, la, lb, lc, ld, name, f_part):
+    """Streaming digestion of one slice of the contracted array.
+
+    acc holds [e|f] for every bra e (la..la+lb) and the ket components f in
+    `f_part` (layout e-major).  The bra horizontal recurrence and spherical
+    transform are applied per f; the ket recurrence and transform are linear,
+    so applying them to the slice (other f taken as zero) gives this slice's
+    share of every spherical value, which is digested at once:
+      K'_ac += d v P_bd, K'_ad += d v P_bc, K'_bc += d v P_ad, K'_bd += d v P_ac.
+    Shares of all slices add up in K' through the atomics."""
+    T = em.T
+    E, F = la + lb, lc + ld
+    e_list = [e for d in range(la, E + 1) for e in cart(d)]
+    eidx = {e: k for k, e in enumerate(e_list)}
+    fidx = {f: k for k, f in enumerate(f_part)}
+    NF = len(f_part)
+    nas, nbs, ncs, nds = 2 * la + 1, 2 * lb + 1, 2 * lc + 1, 2 * ld + 1
+    ax = "xyz"
+    L = em.lines
+    L.append(f"  __device__ __forceinline__ static void {name}(const {T}* __restrict__ acc,")
+    L.append(f"      {T} ABx, {T} ABy, {T} ABz, {T} CDx, {T} CDy, {T} CDz, int a0, int b0, int c0, int d0,")
+    L.append(f"      double deg, const double* __restrict__ P, double* K, int64_t ld) {{")
+    brec, border = hrr_plan(la, lb)
+    krec, korder = hrr_plan(lc, ld)
+    # bra HRR + spherical for every f of the slice
+    for jf, f in enumerate(f_part):
+        names = {}
+        for k, n in enumerate(border):
+            r = brec[n]
+            if r[0] == "base":
+                names[n] = f"acc[{eidx[n[0]] * NF + jf}]"
+                continue
+            nm = f"b{jf}_{k}"
+            names[n] = nm
+            _, i, p1, p2 = r
+            L.append(f"    const {T} {nm} = {names[p1]} + AB{ax[i]} * {names[p2]};")
+        for as_ in range(nas):
+            for bs in range(nbs):
+                terms = []
+                for a, ca in SPH[la][as_].items():
+                    for b, cb in SPH[lb][bs].items():
+                        c = ca * cb
+                        nm = names[(a, b)]
+                        terms.append(nm if c == 1.0 else f"{em.lit(c)} * {nm}")
+                L.append(f"    const {T} s{as_}_{bs}_{jf} = " + " + ".join(terms) + ";")
+    # ket HRR + spherical with the missing f as structural zeros, then digestion
+    for bs in range(nbs):
+        for ks in ("c", "d"):
+            n = ncs if ks == "c" else nds
+            for x in range(n):
+                L.append(f"    double kb{ks}{bs}_{x} = 0.0;")
+    for as_ in range(nas):
+        L.append(f"    {{ const double* Pa = P + (int64_t)(a0 + {as_}) * ld;")
+        L.append("      double kac[%d] = {0}; double kad[%d] = {0};" % (ncs, nds))
+        for bs in range(nbs):
+            L.append(f"      {{ const double* Pb = P + (int64_t)(b0 + {bs}) * ld;")
+            names = {}
+            for k, n in enumerate(korder):
+                r = krec[n]
+                if r[0] == "base":
+                    names[n] = f"s{as_}_{bs}_{fidx[n[0]]}" if n[0] in fidx else None
+                    continue
+                _, i, p1, p2 = r
+                x1, x2 = names[p1], names[p2]
+                if x1 is None and x2 is None:
+                    names[n] = None
+                    continue
+                nm = f"k{as_}_{bs}_{k}"
+                names[n] = nm
+                if x2 is None:
+                    L.append(f"        const {T} {nm} = {x1};")
+                elif x1 is None:
+                    L.append(f"        const {T} {nm} = CD{ax[i]} * {x2};")
+                else:
+                    L.append(f"        const {T} {nm} = {x1} + CD{ax[i]} * {x2};")
+            vals = {}
+            for cs in range(ncs):
+                for ds in range(nds):
+                    terms = []
+                    for c_, cc in SPH[lc][cs].items():
+                        for d_, cd in SPH[ld][ds].items():
+                            c = cc * cd
+                            nm = names[(c_, d_)]
+                            if nm is None:
+                                continue
+                            terms.append(nm if c == 1.0 else f"{em.lit(c)} * {nm}")
+                    if terms:
+                        v = f"v{as_}_{bs}_{cs}_{ds}"
+                        L.append(f"        const double {v} = " + " + ".join(terms) + ";")
+                        vals[(cs, ds)] = v
+            for cs in range(ncs):
+                t1 = [f"{vals[(cs, ds)]} * Pb[d0 + {ds}]" for ds in range(nds) if (cs, ds) in vals]
+                t2 = [f"{vals[(cs, ds)]} * Pa[d0 + {ds}]" for ds in range(nds) if (cs, ds) in vals]
+                if t1:
+                    L.append(f"        kac[{cs}] += " + " + ".join(t1) + ";")
+                    L.append(f"        kbc{bs}_{cs} += " + " + ".join(t2) + ";")
+            for ds in range(nds):
+                t1 = [f"{vals[(cs, ds)]} * Pb[c0 + {cs}]" for cs in range(ncs) if (cs, ds) in vals]
+                t2 = [f"{vals[(cs, ds)]} * Pa[c0 + {cs}]" for cs in range(ncs) if (cs, ds) in vals]
+                if t1:
+                    L.append(f"        kad[{ds}] += " + " + ".join(t1) + ";")
+                    L.append(f"        kbd{bs}_{ds} += " + " + ".join(t2) + ";")
+            L.append("      }")
+        L.append(f"      double* Ka = K + (int64_t)(a0 + {as_}) * ld;")
+        L.append(f"      for (int x = 0; x < {ncs}; ++x) atomicAdd(&Ka[c0 + x], deg * kac[x]);")
+        L.append(f"      for (int x = 0; x < {nds}; ++x) atomicAdd(&Ka[d0 + x], deg * kad[x]);")
+        L.append("    }")
+    for bs in range(nbs):
+        L.append(f"    {{ double* Kb = K + (int64_t)(b0 + {bs}) * ld;")
+        for cs in range(ncs):
+            L.append(f"      atomicAdd(&Kb[c0 + {cs}], deg * kbc{bs}_{cs});")
+        for ds in range(nds):
+            L.append(f"      atomicAdd(&Kb[d0 + {ds}], deg * kbd{bs}_{ds});")
+        L.append("    }")
+    L.append("  }")
+
+
+def best_split(la, lb, lc, ld, G):
+    """Partition the ket f components into G slices.  Candidate orders of the
+    components are tried and the one with the smallest largest-slice
+    recurrence cost is kept."""
+    f_list = [f for d in range(lc, lc + ld + 1) for f in cart(d)]
+    orders = [f_list,
+              sorted(f_list, key=lambda f: (f[2], f[1], f[0])),
+              sorted(f_list, key=lambda f: (-f[0], -f[1], sum(f))),
+              sorted(f_list, key=lambda f: (sum(f), f[2], f[1]))]
+    best = None
+    for od in orders:
+        n = len(od)
+        parts = [od[(g * n) // G:((g + 1) * n) // G] for g in range(G)]
+        costs = [vrr_graph(la, lb, lc, ld, f_targets=p)[4] for p in parts]
+        key = (max(costs), sum(costs))
+        if best is None or key < best[0]:
+            best = (key, parts)
+    return best[1]
+
+
 def split_f(lc, ld, G):
     """Partition the ket f components into G groups of consecutive components."""
     f_list = [f for d in range(lc, lc + ld + 1) for f in cart(d)]
@@ -343,6 +480,17 @@ def split_f(lc, ld, G):
 
 PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 
+# Number of ket slices (waves) per quartet for the classes whose contracted
+# array does not fit one lane's registers.
+DEFAULT_SPLITS = {
+    (2, 1, 1, 1): 2, (2, 1, 2, 0): 2, (2, 2, 1, 0): 2, (2, 2, 2, 0): 4,
+    (2, 1, 2, 1): 4, (2, 2, 1, 1): 4, (2, 2, 2, 1): 8, (2, 2, 2, 2): 16,
+}
+
+# Minimum waves per SIMD asked of the register allocator, per class (classes
+# not listed: 1).
+WAVES = {}
+
 
 def class_tag(c):
     return "".join(str(x) for x in c)
@@ -351,7 +499,7 @@ def class_tag(c):
 def generate(outdir, T="double", splits=None):
     """Write one header and one translation unit per class into outdir and
     return the operation-count model."""
-    splits = splits or {}
+    splits = DEFAULT_SPLITS if splits is None else splits
     os.makedirs(outdir, exist_ok=True)
     suffix = "" if T == "double" else "_f32"
     model = {}
@@ -372,12 +520,34 @@ def generate(outdir, T="double", splits=None):
         _, vflops = emit_vrr(em, la, lb, lc, ld, "vrr")
         G = splits.get((la, lb, lc, ld), 1)
         em.lines.append(f"  static constexpr int NSPLIT = {G};")
+        em.lines.append(f"  static constexpr int WAVES = {WAVES.get((la, lb, lc, ld), 1)};")
         split_cost = []
-        if G > 1:
-            groups = split_f(lc, ld, G)
-            for g, ft in enumerate(groups):
-                _, c = emit_vrr(em, la, lb, lc, ld, f"vrr_part{g}", f_targets=ft)
-                split_cost.append(c)
+        groups = best_split(la, lb, lc, ld, G) if G > 1 else [[f for d in range(lc, F + 1) for f in cart(d)]]
+        nacc_p = []
+        for g, ft in enumerate(groups):
+            n_, c = emit_vrr(em, la, lb, lc, ld, f"vrr_p{g}", f_targets=ft)
+            nacc_p.append(n_)
+            split_cost.append(c)
+            emit_digest_part(em, la, lb, lc, ld, f"dig_p{g}", ft)
+        em.lines.append(f"  static constexpr int NACCP[{G}] = {{{', '.join(str(x) for x in nacc_p)}}};")
+        T_ = em.T
+        em.lines.append("  template <int W> __device__ __forceinline__ static void vrr_p(const %s* __restrict__ g," % T_)
+        em.lines.append("      %s PAx, %s PAy, %s PAz, %s WPx, %s WPy, %s WPz," % ((T_,) * 6))
+        em.lines.append("      %s QCx, %s QCy, %s QCz, %s WQx, %s WQy, %s WQz," % ((T_,) * 6))
+        em.lines.append("      %s i2z, %s roz, %s i2e, %s roe, %s i2ze, %s* __restrict__ acc) {" % ((T_,) * 6))
+        for g_ in range(G):
+            kw = "if" if g_ == 0 else "else if"
+            em.lines.append(f"    {kw} constexpr (W == {g_}) vrr_p{g_}(g, PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz,"
+                            " WQx, WQy, WQz, i2z, roz, i2e, roe, i2ze, acc);")
+        em.lines.append("  }")
+        em.lines.append("  template <int W> __device__ __forceinline__ static void dig(const %s* __restrict__ acc," % T_)
+        em.lines.append("      %s ABx, %s ABy, %s ABz, %s CDx, %s CDy, %s CDz, int a0, int b0, int c0, int d0," % ((T_,) * 6))
+        em.lines.append("      double deg, const double* __restrict__ P, double* K, int64_t ld) {")
+        for g_ in range(G):
+            kw = "if" if g_ == 0 else "else if"
+            em.lines.append(f"    {kw} constexpr (W == {g_}) dig_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, a0, b0, c0, d0,"
+                            " deg, P, K, ld);")
+        em.lines.append("  }")
         pflops = emit_post(em, la, lb, lc, ld)
         em.lines.append("};")
         with open(os.path.join(outdir, f"eri_{tag}{suffix}.h"), "w") as f:
@@ -391,7 +561,7 @@ def generate(outdir, T="double", splits=None):
             f'#include "eri_{tag}{suffix}.h"',
             "namespace hfx {",
             f"void launch_eri_{tag}(const QuartetArgs &a, unsigned nblk, hipStream_t s) {{",
-            f"  hipLaunchKernelGGL(k_eri<{nm}>, dim3(nblk), dim3(64), 0, s, a);",
+            f"  hipLaunchKernelGGL(k_eri<{nm}>, dim3(nblk * {nm}::NSPLIT), dim3(64), 0, s, a);",
             "}",
             f"void launch_eval_{tag}(const PairHdr *h, const PrimRec *p, const int32_t *bk, int n, int op,",
             "                    double om2, const double *tab, double *out, hipStream_t s) {",
@@ -403,6 +573,10 @@ def generate(outdir, T="double", splits=None):
                 f"void launch_schwarz_{class_tag((la, lb))}(const PairHdr *h, const PrimRec *p, const int32_t *ids, int n,",
                 "                    int op, double om2, const double *tab, double *Q, hipStream_t s) {",
                 f"  hipLaunchKernelGGL(k_schwarz<{nm}>, dim3((n + 63) / 64), dim3(64), 0, s, h, p, ids, n, op, om2, tab, Q);",
+                "}",
+                f"void launch_primbound_{class_tag((la, lb))}(const PairHdr *h, PrimRec *p, const int32_t *ids, int n,",
+                "                    int op, double om2, const double *tab, hipStream_t s) {",
+                f"  hipLaunchKernelGGL(k_primbound<{nm}>, dim3((n + 63) / 64), dim3(64), 0, s, h, p, ids, n, op, om2, tab);",
                 "}",
             ]
         tu.append("}  // namespace hfx")

@@ -8,7 +8,10 @@
 //            Gaussian product centre P, P - A and the scaled prefactor
 //            sqrt(2) pi^(5/4) c_a c_b exp(-a b |AB|^2 / zeta) / zeta, so that
 //            the [00|00] prefactor 2 pi^(5/2)/(zeta eta sqrt(zeta+eta)) K_AB
-//            K_CD is the product of two records over sqrt(zeta + eta).
+//            K_CD is the product of two records over sqrt(zeta + eta); and the
+//            primitive pair's own Schwarz factor B, so that every primitive
+//            quartet contributes at most B_ab B_cd to any integral.  The
+//            records of a pair are sorted by B, largest first.
 //   Boys     table T_L[i][k] = F_(L+k)(i h) / k!, h = 1/16, i <= 576, k < 8,
 //            one 8-double row per grid point and L.
 #pragma once
@@ -28,7 +31,8 @@ struct PairHdr {
 };
 
 struct PrimRec {
-    double z, i2z, Px, Py, Pz, PAx, PAy, PAz, K, pad;
+    double z, i2z, Px, Py, Pz, PAx, PAy, PAz, K;
+    double B;  // Schwarz factor of this primitive pair alone (records of a pair sorted by B, descending)
 };
 
 constexpr int BOYS_NROW = 577;          // grid points 0 .. 36 step 1/16
@@ -110,6 +114,41 @@ __device__ __forceinline__ void prim_quartet(const PrimRec &b, double kz, double
     }
     const double re = kz * ize, rz = b.z * ize;  // rho/zeta, rho/eta
     C::vrr(g, b.PAx, b.PAy, b.PAz, -re * PQx, -re * PQy, -re * PQz, kQCx, kQCy, kQCz,
+           rz * PQx, rz * PQy, rz * PQz, b.i2z, re, ki2z, rz, 0.5 * ize, acc);
+}
+
+template <class C, int W>
+__device__ __forceinline__ void prim_quartet_p(const PrimRec &b, double kz, double ki2z, double kPx,
+                                             double kPy, double kPz, double kQCx, double kQCy,
+                                             double kQCz, double kK, int op, double om2,
+                                             const double *__restrict__ tab, double *acc) {
+    const double ze = b.z + kz;
+    const double rs = rsqrt(ze);
+    const double ize = rs * rs;
+    const double rho = b.z * kz * ize;
+    const double PQx = b.Px - kPx, PQy = b.Py - kPy, PQz = b.Pz - kPz;
+    const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    const double pref = b.K * kK * rs;
+    double g[C::L + 1];
+    boys<C::L>(T, tab, g);
+    if (op) {
+        const double tr = rsqrt(om2 + rho);
+        const double th = sqrt(om2) * tr;   // theta
+        const double th2 = th * th;
+        double g2[C::L + 1];
+        boys<C::L>(th2 * T, tab, g2);
+        double f = th * pref;
+#pragma unroll
+        for (int m = 0; m <= C::L; ++m) {
+            g[m] = fma(-f, g2[m], pref * g[m]);
+            f *= th2;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m <= C::L; ++m) g[m] *= pref;
+    }
+    const double re = kz * ize, rz = b.z * ize;  // rho/zeta, rho/eta
+    C::template vrr_p<W>(g, b.PAx, b.PAy, b.PAz, -re * PQx, -re * PQy, -re * PQz, kQCx, kQCy, kQCz,
            rz * PQx, rz * PQy, rz * PQz, b.i2z, re, ki2z, rz, 0.5 * ize, acc);
 }
 
@@ -199,6 +238,7 @@ struct QuartetArgs {
     double tau;
     int32_t op;
     double om2;               // omega^2
+    double prim_tau;          // primitive quartets with B_ab B_cd < prim_tau may be skipped
     const double *boys;
     const double *P;
     double *K;
@@ -226,52 +266,79 @@ __device__ __forceinline__ int ket_cut(const QuartetArgs &a, int p, int g, int *
     return l;
 }
 
-// Lane-per-quartet kernel of class C: block = one bra pair and one ket group,
-// 64 lanes walk the screened ket range; bra primitive data is uniform.
-template <class C>
-__global__ __launch_bounds__(64) void k_eri(QuartetArgs a) {
-    const int j = blockIdx.x / a.n_kgrp;
-    const int g = blockIdx.x - j * a.n_kgrp;
-    const int p = a.bra_first + j * a.bra_stride;
-    if (p >= a.n_bra) return;
-    int lo = 0;
-    const int cut = ket_cut(a, p, g, &lo);
-    if (cut <= lo) return;
+// One wave's work on one tile: 64 lanes walk the screened ket range of bra
+// pair p in ket group g; each lane holds slice W of one quartet's contracted
+// array, accumulated over all primitive quartets, and digests that slice's
+// share of the quartet.
+template <class C, int W, int VRRW>
+__device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, int lo, int cut) {
     const PairHdr bh = a.hdr[a.bra_ids[p]];
     const int nkp = a.ket_gnp[g];
     const int lane = threadIdx.x;
-    if (lane == 0 && a.count) {
-        const unsigned long long nq = (unsigned long long)(cut - lo);
-        atomicAdd(&a.count[0], nq);
-        atomicAdd(&a.count[1], nq * (unsigned long long)(bh.n * nkp));
-    }
-    constexpr int NA = 2 * C::LA + 1, NB = 2 * C::LB + 1, NC = 2 * C::LC + 1, ND = 2 * C::LD + 1;
+    const double eps = a.prim_tau;
+    const double bmax = a.prim[bh.off].B;
+    constexpr int NA = C::NACCP[W];
+    unsigned long long nprim = 0;
     for (int q0 = lo; q0 < cut; q0 += 64) {
         const int q = q0 + lane;
         const bool act = q < cut;
         const int kid = a.ket_ids[act ? q : lo];
         const PairHdr kh = a.hdr[kid];
-        double acc[C::NACC];
+        double acc[NA];
 #pragma unroll
-        for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
+        for (int i = 0; i < NA; ++i) acc[i] = 0.0;
         for (int kp = 0; kp < nkp; ++kp) {
             const PrimRec k = a.prim[kh.off + kp];
+            const double kb = act ? k.B : 0.0;
+            // records are sorted by B: once no lane can reach eps, none will
+            if (!__any(kb * bmax >= eps)) break;
             for (int bp = 0; bp < bh.n; ++bp) {
                 const PrimRec b = a.prim[bh.off + bp];
-                prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, a.op, a.om2,
-                                a.boys, acc);
+                if (!__any(kb * b.B >= eps)) break;
+                nprim += act;
+                prim_quartet_p<C, W>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, a.op, a.om2,
+                                     a.boys, acc);
             }
         }
-        double out[C::NOUT];
-        C::post(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, out);
         if (act) {
             double deg = 1.0;
             if (bh.diag) deg *= 0.5;
             if (kh.diag) deg *= 0.5;
             if (bh.id == kh.id) deg *= 0.5;
-            digest<NA, NB, NC, ND>(out, bh.bfA, bh.bfB, kh.bfA, kh.bfB, deg, a.P, a.K, a.ld);
+            C::template dig<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB, kh.bfA,
+                               kh.bfB, deg, a.P, a.K, a.ld);
         }
     }
+    if (W == 0 && a.count && nprim) atomicAdd(&a.count[1], nprim);
+}
+
+template <class C, int W>
+__device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p, int g, int lo, int cut) {
+    if (w == W) {
+        tile_part<C, W, W>(a, p, g, lo, cut);
+    } else if constexpr (W + 1 < C::NSPLIT) {
+        tile_dispatch<C, W + 1>(a, w, p, g, lo, cut);
+    }
+}
+
+// Quartet kernel of class C.  Block = (bra slot, ket group, slice): a class
+// whose contracted array is too large for one lane is cut into NSPLIT slices
+// of ket components, each evaluated by its own wave (the waves of one tile
+// are adjacent block indices); the common part of the recurrence is
+// recomputed per slice instead of exchanged.
+template <class C>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri(QuartetArgs a) {
+    const int w = blockIdx.x % C::NSPLIT;
+    const int t = blockIdx.x / C::NSPLIT;
+    const int j = t / a.n_kgrp;
+    const int g = t - j * a.n_kgrp;
+    const int p = a.bra_first + j * a.bra_stride;
+    if (p >= a.n_bra) return;
+    int lo = 0;
+    const int cut = ket_cut(a, p, g, &lo);
+    if (cut <= lo) return;
+    if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut - lo));
+    tile_dispatch<C, 0>(a, w, p, g, lo, cut);
 }
 
 // Schwarz factor of each pair of one pair class: Q = sqrt(max diagonal (ij|ij)).
@@ -303,6 +370,43 @@ __global__ __launch_bounds__(64) void k_schwarz(const PairHdr *__restrict__ hdr,
 #pragma unroll
         for (int j = 0; j < NB; ++j) mx = fmax(mx, out[((i * NB + j) * NA + i) * NB + j]);
     Q[h.id] = sqrt(mx);
+}
+
+// Schwarz factor B of every primitive pair of the pairs of one pair class
+// (the diagonal integral of the single primitive pair, spherical), then the
+// records of each pair sorted by B, largest first.
+template <class C>
+__global__ __launch_bounds__(64) void k_primbound(const PairHdr *__restrict__ hdr, PrimRec *__restrict__ prim,
+                                                  const int32_t *__restrict__ ids, int n, int op, double om2,
+                                                  const double *__restrict__ tab) {
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t >= n) return;
+    const PairHdr h = hdr[ids[t]];
+    constexpr int NA = 2 * C::LA + 1, NB = 2 * C::LB + 1;
+    for (int r = 0; r < h.n; ++r) {
+        const PrimRec x = prim[h.off + r];
+        double acc[C::NACC];
+#pragma unroll
+        for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
+        prim_quartet<C>(x, x.z, x.i2z, x.Px, x.Py, x.Pz, x.PAx, x.PAy, x.PAz, x.K, op, om2, tab, acc);
+        double out[C::NOUT];
+        C::post(acc, h.ABx, h.ABy, h.ABz, h.ABx, h.ABy, h.ABz, out);
+        double mx = 0.0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) mx = fmax(mx, out[((i * NB + j) * NA + i) * NB + j]);
+        prim[h.off + r].B = sqrt(mx);
+    }
+    for (int i = 1; i < h.n; ++i) {  // insertion sort by B, descending
+        const PrimRec x = prim[h.off + i];
+        int j = i - 1;
+        while (j >= 0 && prim[h.off + j].B < x.B) {
+            prim[h.off + j + 1] = prim[h.off + j];
+            --j;
+        }
+        prim[h.off + j + 1] = x;
+    }
 }
 
 // Raw integrals of listed quartets (canonical pair ids bra, ket), one per lane.

@@ -124,7 +124,7 @@ __global__ void k_pairdata(const PairHdr *__restrict__ hdr, const int32_t *__res
             p.PAy = p.Py - A.y;
             p.PAz = p.Pz - A.z;
             p.K = c0 * ca * cb * exp(-a * b * iz * ab2) * iz;
-            p.pad = 0.0;
+            p.B = 0.0;
             out[r++] = p;
         }
     }
@@ -193,6 +193,12 @@ void launch_schwarz_11(const PairHdr *, const PrimRec *, const int32_t *, int, i
 void launch_schwarz_20(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
 void launch_schwarz_21(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
 void launch_schwarz_22(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
+#define PB(T) void launch_primbound_##T(const PairHdr *, PrimRec *, const int32_t *, int, int, double, const double *, hipStream_t);
+PB(00) PB(10) PB(11) PB(20) PB(21) PB(22)
+#undef PB
+typedef void (*primbound_fn)(const PairHdr *, PrimRec *, const int32_t *, int, int, double, const double *, hipStream_t);
+static const primbound_fn k_primbound_tab[6] = {launch_primbound_00, launch_primbound_10, launch_primbound_11,
+                                                launch_primbound_20, launch_primbound_21, launch_primbound_22};
 
 typedef void (*eri_fn)(const QuartetArgs &, unsigned, hipStream_t);
 typedef void (*eval_fn)(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *,
@@ -250,7 +256,7 @@ static hfx_status check_opts(const hfx_opts *o) {
     if (!(o->omega >= 0.0) || !std::isfinite(o->omega)) return fail(HFX_EINVAL, "omega must be finite and >= 0");
     if (o->prec != HFX_PREC_FP64 && o->prec != HFX_PREC_MIXED) return fail(HFX_EINVAL, "unknown precision mode");
     if (o->prec == HFX_PREC_MIXED && !(o->mixed_cut >= 0.0)) return fail(HFX_EINVAL, "mixed_cut must be >= 0");
-    if (o->prim_tau != 0.0) return fail(HFX_EINVAL, "prim_tau is reserved and must be 0");
+    if (!(o->prim_tau >= 0.0) || !std::isfinite(o->prim_tau)) return fail(HFX_EINVAL, "prim_tau must be finite and >= 0");
     if (o->flags != 0) return fail(HFX_EINVAL, "flags are reserved and must be 0");
     return HFX_OK;
 }
@@ -444,6 +450,7 @@ hfx_status compute_bounds(hfx_pairs p, const hfx_opts *o, hipStream_t st) {
             return fail(HFX_EDEVICE, std::string("bounds copy: ") + hipGetErrorString(e));
         }
         k_schwarz_tab[c](p->d_hdr, p->d_prim, d_ids + off, (int)ids.size(), op, om2, p->d_boys, p->d_Q, st);
+        k_primbound_tab[c](p->d_hdr, p->d_prim, d_ids + off, (int)ids.size(), op, om2, p->d_boys, st);
         off += mx;
     }
     hipError_t e = hipGetLastError();
@@ -568,6 +575,7 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             a.tau = o->tau;
             a.op = op;
             a.om2 = op ? o->omega * o->omega : 0.0;
+            a.prim_tau = o->prim_tau;
             a.boys = p->d_boys;
             a.P = P;
             a.K = K;

@@ -56,6 +56,7 @@ def test_invalid_basis_rejected_on_host(mutate, status):
     (dict(tau=-1.0), hfx.HFX_EINVAL),
     (dict(omega=-0.1, op=hfx.OP_ERFC), hfx.HFX_EINVAL),
     (dict(prec=7), hfx.HFX_EINVAL),
+    (dict(prim_tau=-1.0), hfx.HFX_EINVAL),
 ])
 def test_invalid_options_rejected_on_host(kw, status):
     s = hi.config0()

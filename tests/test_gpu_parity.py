@@ -31,11 +31,11 @@ def _device():
     torch.cuda.init()
 
 
-def _gpu_K(s, tau, omega, stats=False):
+def _gpu_K(s, tau, omega, stats=False, prim_tau=None):
     p = hfx.pairs_from_system(s, hfx.opts(tau=tau, omega=omega))
     P = torch.from_numpy(s.P).cuda()
     K = torch.empty_like(P)
-    st = hfx.build_K(p, P, K, hfx.opts(tau=tau, omega=omega), stats=stats)
+    st = hfx.build_K(p, P, K, hfx.opts(tau=tau, omega=omega, prim_tau=prim_tau), stats=stats)
     torch.cuda.synchronize()
     return K.cpu().numpy(), st, p
 
@@ -91,31 +91,53 @@ def test_raw_integrals_every_class(omega):
     assert len(seen) == 21, len(seen)
 
 
+@pytest.mark.parametrize("prim_tau", [0.0, None])
 @pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
-def test_K_config0(omega):
+def test_K_config0(omega, prim_tau):
+    """prim_tau = 0: every primitive quartet (same counts as the oracle);
+    default: primitive quartets with bound below 1e-6 tau skipped."""
     s = hi.config0()
-    _say("K config0", omega)
+    _say("K config0", omega, prim_tau)
     Ko, _, cnt = oracle.build_K(s, tau=1e-10, omega=omega)
-    Kg, st, _ = _gpu_K(s, 1e-10, omega, stats=True)
+    Kg, st, _ = _gpu_K(s, 1e-10, omega, stats=True, prim_tau=prim_tau)
+    _say("  max |dK|", np.abs(Kg - Ko).max(), "prim quartets", st["prim_quartets"], "of", cnt["prim_quartets"])
     assert np.abs(Kg - Ko).max() <= 1e-10
     assert np.abs(Kg - Kg.T).max() == 0.0
     assert st["quartets"] == cnt["quartets"]
-    assert st["prim_quartets"] == cnt["prim_quartets"]
+    if prim_tau == 0.0:
+        assert st["prim_quartets"] == cnt["prim_quartets"]
+    else:
+        assert st["prim_quartets"] <= cnt["prim_quartets"]
     assert abs(np.trace(s.P @ Kg) - np.trace(s.P @ Ko)) <= 1e-10 * abs(np.trace(s.P @ Ko))
 
 
+@pytest.mark.parametrize("prim_tau", [0.0, None])
 @pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
 @pytest.mark.parametrize("tau", [0.0, 1e-10, 1e-6])
-def test_K_dzp_small(omega, tau):
+def test_K_dzp_small(omega, tau, prim_tau):
     """s, p and d shells; ket ranges longer than one 64-lane chunk with a
-    ragged tail; tau = 0 (every quartet), tight and loose screening."""
+    ragged tail; tau = 0 (every quartet), tight and loose screening; with
+    and without primitive-quartet skipping."""
     s = _spd_small(seed=23, natom=8, nprim=(1, 3))
-    _say("K dzp8", omega, tau)
+    _say("K dzp8", omega, tau, prim_tau)
     Ko, _, cnt = oracle.build_K(s, tau=tau, omega=omega)
-    Kg, st, _ = _gpu_K(s, tau, omega, stats=True)
+    Kg, st, _ = _gpu_K(s, tau, omega, stats=True, prim_tau=prim_tau)
+    _say("  max |dK|", np.abs(Kg - Ko).max())
     assert np.abs(Kg - Ko).max() <= 1e-10, np.abs(Kg - Ko).max()
     assert st["quartets"] == cnt["quartets"]
     assert list(st["class_quartets"]) == list(cnt["per_class"])
+
+
+def test_prim_skipping_error_dzp_full_contraction():
+    """3-6 primitives per shell (the workload's contraction): the skipped
+    primitive quartets change K by far less than the 1e-10 bar."""
+    s = hi.lattice_system(6, seed=31)
+    Ko, _, cnt = oracle.build_K(s, tau=1e-10, omega=hi.OMEGA_HSE)
+    Kg, st, _ = _gpu_K(s, 1e-10, hi.OMEGA_HSE, stats=True)
+    err = np.abs(Kg - Ko).max()
+    _say("dzp6 full contraction: max |dK|", err, "prim", st["prim_quartets"], "of", cnt["prim_quartets"])
+    assert err <= 1e-11
+    assert st["prim_quartets"] < cnt["prim_quartets"]
 
 
 def test_K_degenerate_single_shell_and_s_only():
