@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--natom", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle timing leg")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--mixed-cut", type=float, default=1e-6, help="tuned FP32 cut on Q_IJ Q_KL")
     return ap.parse_args()
 
 
@@ -172,6 +174,29 @@ def main():
             "traffic": None,
         },
     }
+    if not a.no_mixed:
+        # mixed precision on the same shard: quartets with bound < cut in FP32
+        om = hfx.opts(tau=tau, omega=omega, prec=hfx.PREC_MIXED, mixed_cut=a.mixed_cut)
+        Km = torch.empty_like(P)
+        hfx.build_K_shard(pairs, P, Km, om, a.shard, a.shards)  # warm-up (FP32 record copies)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stm = hfx.build_K_shard(pairs, P, Km, om, a.shard, a.shards, stats=True)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        print(f"# mixed step: {tm:.3f} s", file=sys.stderr, flush=True)
+        Kmh = Km.cpu().numpy()
+        Ph = sysm.P
+        out["mixed"] = {
+            "value": stm["quartets"] / tm,
+            "unit": "quartets/s",
+            "ms_per_step": 1e3 * tm,
+            "speedup_vs_fp64": (1e3 * tm) and ms / (1e3 * tm),
+            "mixed_cut": a.mixed_cut,
+            "fp32_quartet_fraction": stm["quartets_fp32"] / max(1, stm["quartets"]),
+            "max_abs_dK_vs_fp64_gpu": float(np.abs(Kmh - Kh).max()),
+            "trPK_err_vs_fp64_gpu": float(abs(np.sum(Ph * Kmh) - np.sum(Ph * Kh))),
+        }
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sysm, tau, omega, a.cpu_seconds)
     print(json.dumps(out), flush=True)

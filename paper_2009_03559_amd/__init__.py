@@ -108,7 +108,10 @@ def _check(rc):
 PRIM_TAU_REL = 1e-6  # default primitive-quartet threshold relative to tau
 
 
-def opts(tau=1e-10, omega=0.0, prec=PREC_FP64, mixed_cut=1e-5, op=None, prim_tau=None) -> Opts:
+MIXED_CUT = 1e-6  # tuned: measured max |dK| ~1e-9..3e-8 (1e-5 gives ~2e-5)
+
+
+def opts(tau=1e-10, omega=0.0, prec=PREC_FP64, mixed_cut=MIXED_CUT, op=None, prim_tau=None) -> Opts:
     """Options; prim_tau defaults to 1e-6 tau (0 = every primitive quartet)."""
     if op is None:
         op = OP_ERFC if omega > 0 else OP_COULOMB

@@ -487,6 +487,9 @@ DEFAULT_SPLITS = {
     (2, 1, 2, 1): 4, (2, 2, 1, 1): 4, (2, 2, 2, 1): 8, (2, 2, 2, 2): 16,
 }
 
+# FP32 slices: the same as FP64 (fewer slices spill in FP32 too).
+DEFAULT_SPLITS_F32 = dict(DEFAULT_SPLITS)
+
 # Minimum waves per SIMD asked of the register allocator, per class (classes
 # not listed: 1).
 WAVES = {}
@@ -499,7 +502,8 @@ def class_tag(c):
 def generate(outdir, T="double", splits=None):
     """Write one header and one translation unit per class into outdir and
     return the operation-count model."""
-    splits = DEFAULT_SPLITS if splits is None else splits
+    if splits is None:
+        splits = DEFAULT_SPLITS if T == "double" else DEFAULT_SPLITS_F32
     os.makedirs(outdir, exist_ok=True)
     suffix = "" if T == "double" else "_f32"
     model = {}
@@ -555,6 +559,20 @@ def generate(outdir, T="double", splits=None):
         model[tag] = dict(vrr_flops=vflops, post_flops=pflops, nacc=NE * NF,
                           nout=nsph, split=G, split_vrr_flops=split_cost)
         diag = (la, lb) == (lc, ld)
+        if T != "double":
+            tu = [
+                "// Generated by gen_eri.py; do not edit.",
+                '#include "hfx_device.hpp"',
+                f'#include "eri_{tag}{suffix}.h"',
+                "namespace hfx {",
+                f"void launch_eri32_{tag}(const QuartetArgs &a, unsigned nblk, hipStream_t s) {{",
+                f"  hipLaunchKernelGGL(k_eri32<{nm}>, dim3(nblk * {nm}::NSPLIT), dim3(64), 0, s, a);",
+                "}",
+            ]
+            tu.append("}  // namespace hfx")
+            with open(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "w") as f:
+                f.write("\n".join(tu) + "\n")
+            continue
         tu = [
             "// Generated by gen_eri.py; do not edit.",
             '#include "hfx_device.hpp"',
@@ -618,7 +636,8 @@ def main():
     ap.add_argument("--type", default="double")
     ap.add_argument("--model", default=None)
     a = ap.parse_args()
-    model = generate(a.outdir, a.type)
+    model = generate(a.outdir, "double")
+    generate(a.outdir, "float")
     write_model(a.outdir, model)
     if a.model:
         with open(a.model, "w") as f:

@@ -35,6 +35,11 @@ struct PrimRec {
     double B;  // Schwarz factor of this primitive pair alone (records of a pair sorted by B, descending)
 };
 
+// FP32 copy of a record, used for quartets evaluated in FP32 (mixed mode).
+struct PrimRec32 {
+    float z, i2z, Px, Py, Pz, PAx, PAy, PAz, K, B;
+};
+
 constexpr int BOYS_NROW = 577;          // grid points 0 .. 36 step 1/16
 constexpr double BOYS_H = 1.0 / 16.0;
 constexpr double BOYS_INVH = 16.0;
@@ -75,6 +80,35 @@ __device__ __forceinline__ void boys(double x, const double *__restrict__ tab, d
         const double h = 0.5 * rs * rs;       // 1/(2x)
 #pragma unroll
         for (int m = 0; m < L; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -ex) * h;
+    }
+}
+
+// FP32 Boys: x < 36 from the FP32 table (Taylor to fourth order around the
+// nearest grid point, |u| <= 1/32, truncation below 3e-10 relative) and the
+// downward recursion in FP32; x >= 36 in FP64 (F_0 then upward), rounded.
+template <int L>
+__device__ __forceinline__ void boys32(float x, const float *__restrict__ tab, float *F) {
+    if (x < (float)BOYS_TMAX) {
+        const float ex = __expf(-x);
+        const int i = __float2int_rn(x * (float)BOYS_INVH);
+        const float u = (float)i * (float)BOYS_H - x;
+        const float *r = tab + ((size_t)L * BOYS_NROW + i) * BOYS_NTAY;
+        const float4 lo = *reinterpret_cast<const float4 *>(r);
+        const float e4 = r[4];
+        float f = e4;
+        f = fmaf(f, u, lo.w);
+        f = fmaf(f, u, lo.z);
+        f = fmaf(f, u, lo.y);
+        f = fmaf(f, u, lo.x);
+        F[L] = f;
+        const float x2 = 2.0f * x;
+#pragma unroll
+        for (int m = L - 1; m >= 0; --m) F[m] = fmaf(x2, F[m + 1], ex) * (1.0f / (2 * m + 1));
+    } else {
+        double Fd[L + 1];
+        boys<L>((double)x, nullptr, Fd);  // large-x branch only: no table access
+#pragma unroll
+        for (int m = 0; m <= L; ++m) F[m] = (float)Fd[m];
     }
 }
 
@@ -150,6 +184,39 @@ __device__ __forceinline__ void prim_quartet_p(const PrimRec &b, double kz, doub
     const double re = kz * ize, rz = b.z * ize;  // rho/zeta, rho/eta
     C::template vrr_p<W>(g, b.PAx, b.PAy, b.PAz, -re * PQx, -re * PQy, -re * PQz, kQCx, kQCy, kQCz,
            rz * PQx, rz * PQy, rz * PQz, b.i2z, re, ki2z, rz, 0.5 * ize, acc);
+}
+
+// FP32 primitive quartet (slice W of class C in FP32).
+template <class C, int W>
+__device__ __forceinline__ void prim_quartet32(const PrimRec32 &b, const PrimRec32 &k, int op, float om,
+                                               float om2, const float *__restrict__ tab, float *acc) {
+    const float ze = b.z + k.z;
+    const float rs = rsqrtf(ze);
+    const float ize = rs * rs;
+    const float rho = b.z * k.z * ize;
+    const float PQx = b.Px - k.Px, PQy = b.Py - k.Py, PQz = b.Pz - k.Pz;
+    const float T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    const float pref = b.K * k.K * rs;
+    float g[C::L + 1];
+    boys32<C::L>(T, tab, g);
+    if (op) {
+        const float th = om * rsqrtf(om2 + rho);
+        const float th2 = th * th;
+        float g2[C::L + 1];
+        boys32<C::L>(th2 * T, tab, g2);
+        float f = th * pref;
+#pragma unroll
+        for (int m = 0; m <= C::L; ++m) {
+            g[m] = fmaf(-f, g2[m], pref * g[m]);
+            f *= th2;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m <= C::L; ++m) g[m] *= pref;
+    }
+    const float re = k.z * ize, rz = b.z * ize;
+    C::template vrr_p<W>(g, b.PAx, b.PAy, b.PAz, -re * PQx, -re * PQy, -re * PQz, k.PAx, k.PAy, k.PAz,
+                         rz * PQx, rz * PQy, rz * PQz, b.i2z, re, k.i2z, rz, 0.5f * ize, acc);
 }
 
 // Digestion of one contracted quartet (AB|CD) with spherical values v[a][b][c][d]:
@@ -235,18 +302,32 @@ struct QuartetArgs {
     const int32_t *ket_gnp;   // primitive-pair count of each ket group
     int32_t n_kgrp;
     int32_t same;             // bra class == ket class: quartet (p,q) needs q <= p
-    double tau;
+    double tau;               // ket range: tau <= Q_p Q_q < tau_hi
+    double tau_hi;
     int32_t op;
     double om2;               // omega^2
     double prim_tau;          // primitive quartets with B_ab B_cd < prim_tau may be skipped
     const double *boys;
+    const PrimRec32 *prim32;  // FP32 records and table (FP32 launches)
+    const float *boys32;
     const double *P;
     double *K;
     int64_t ld;
-    unsigned long long *count;  // [0] quartets, [1] primitive quartets
+    unsigned long long *count;  // [0] quartets, [1] primitive quartets of this launch
 };
 
-// Ket range of block (p, g): slots [lo, cut) of ket group g with Q_p Q_q >= tau.
+// First slot q in [l, h) with !(Qp Q[q] >= t); Q is sorted descending.
+__device__ __forceinline__ int first_below(const double *Q, int l, int h, double Qp, double t) {
+    while (l < h) {
+        const int m = (l + h) >> 1;
+        if (Qp * Q[m] >= t) l = m + 1;
+        else h = m;
+    }
+    return l;
+}
+
+// Ket range of block (p, g): slots [lo, cut) of ket group g with
+// tau <= Q_p Q_q < tau_hi (and q <= p inside one class).
 __device__ __forceinline__ int ket_cut(const QuartetArgs &a, int p, int g, int *lo_out) {
     const double Qp = a.bra_Q[p];
     int lo = a.ket_goff[g], hi = a.ket_goff[g + 1];
@@ -256,14 +337,9 @@ __device__ __forceinline__ int ket_cut(const QuartetArgs &a, int p, int g, int *
         if (g > gp) return lo;  // empty: every slot of group g is after p
         if (g == gp) hi = p + 1;
     }
-    // Q descending: first q with !(Qp*Q[q] >= tau)
-    int l = lo, h = hi;
-    while (l < h) {
-        const int m = (l + h) >> 1;
-        if (Qp * a.ket_Q[m] >= a.tau) l = m + 1;
-        else h = m;
-    }
-    return l;
+    lo = first_below(a.ket_Q, lo, hi, Qp, a.tau_hi);
+    *lo_out = lo;
+    return first_below(a.ket_Q, lo, hi, Qp, a.tau);
 }
 
 // One wave's work on one tile: 64 lanes walk the screened ket range of bra
@@ -339,6 +415,73 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     if (cut <= lo) return;
     if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut - lo));
     tile_dispatch<C, 0>(a, w, p, g, lo, cut);
+}
+
+// FP32 counterpart of tile_part: FP32 records, recurrences and contraction,
+// FP64 digestion into K.
+template <class C, int W>
+__device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, int lo, int cut) {
+    const PairHdr bh = a.hdr[a.bra_ids[p]];
+    const int nkp = a.ket_gnp[g];
+    const int lane = threadIdx.x;
+    const float eps = (float)a.prim_tau;
+    const float bmax = a.prim32[bh.off].B;
+    const float om2 = (float)a.om2, om = sqrtf(om2);
+    constexpr int NA = C::NACCP[W];
+    unsigned long long nprim = 0;
+    for (int q0 = lo; q0 < cut; q0 += 64) {
+        const int q = q0 + lane;
+        const bool act = q < cut;
+        const int kid = a.ket_ids[act ? q : lo];
+        const PairHdr kh = a.hdr[kid];
+        float acc[NA];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) acc[i] = 0.0f;
+        for (int kp = 0; kp < nkp; ++kp) {
+            const PrimRec32 k = a.prim32[kh.off + kp];
+            const float kb = act ? k.B : 0.0f;
+            if (!__any(kb * bmax >= eps)) break;
+            for (int bp = 0; bp < bh.n; ++bp) {
+                const PrimRec32 b = a.prim32[bh.off + bp];
+                if (!__any(kb * b.B >= eps)) break;
+                nprim += act;
+                prim_quartet32<C, W>(b, k, a.op, om, om2, a.boys32, acc);
+            }
+        }
+        if (act) {
+            double deg = 1.0;
+            if (bh.diag) deg *= 0.5;
+            if (kh.diag) deg *= 0.5;
+            if (bh.id == kh.id) deg *= 0.5;
+            C::template dig<W>(acc, (float)bh.ABx, (float)bh.ABy, (float)bh.ABz, (float)kh.ABx, (float)kh.ABy,
+                               (float)kh.ABz, bh.bfA, bh.bfB, kh.bfA, kh.bfB, deg, a.P, a.K, a.ld);
+        }
+    }
+    if (W == 0 && a.count && nprim) atomicAdd(&a.count[1], nprim);
+}
+
+template <class C, int W>
+__device__ __forceinline__ void tile_dispatch32(const QuartetArgs &a, int w, int p, int g, int lo, int cut) {
+    if (w == W) {
+        tile_part32<C, W>(a, p, g, lo, cut);
+    } else if constexpr (W + 1 < C::NSPLIT) {
+        tile_dispatch32<C, W + 1>(a, w, p, g, lo, cut);
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri32(QuartetArgs a) {
+    const int w = blockIdx.x % C::NSPLIT;
+    const int t = blockIdx.x / C::NSPLIT;
+    const int j = t / a.n_kgrp;
+    const int g = t - j * a.n_kgrp;
+    const int p = a.bra_first + j * a.bra_stride;
+    if (p >= a.n_bra) return;
+    int lo = 0;
+    const int cut = ket_cut(a, p, g, &lo);
+    if (cut <= lo) return;
+    if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut - lo));
+    tile_dispatch32<C, 0>(a, w, p, g, lo, cut);
 }
 
 // Schwarz factor of each pair of one pair class: Q = sqrt(max diagonal (ij|ij)).

@@ -74,20 +74,30 @@ static std::vector<double> make_boys_table() {
 
 static std::mutex g_boys_mu;
 static std::vector<double *> g_boys_dev;  // per device
+static std::vector<float *> g_boys32_dev;  // per device: the same table rounded to FP32
 
-static hfx_status boys_table(const double **out) {
+static hfx_status boys_table(const double **out, const float **out32) {
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_boys_mu);
-    if ((int)g_boys_dev.size() <= dev) g_boys_dev.resize(dev + 1, nullptr);
+    if ((int)g_boys_dev.size() <= dev) {
+        g_boys_dev.resize(dev + 1, nullptr);
+        g_boys32_dev.resize(dev + 1, nullptr);
+    }
     if (!g_boys_dev[dev]) {
         std::vector<double> t = make_boys_table();
+        std::vector<float> t32(t.begin(), t.end());
         double *d = nullptr;
+        float *d32 = nullptr;
         HIPCHK(hipMalloc(&d, t.size() * sizeof(double)));
         HIPCHK(hipMemcpy(d, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMalloc(&d32, t32.size() * sizeof(float)));
+        HIPCHK(hipMemcpy(d32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
         g_boys_dev[dev] = d;
+        g_boys32_dev[dev] = d32;
     }
     *out = g_boys_dev[dev];
+    *out32 = g_boys32_dev[dev];
     return HFX_OK;
 }
 
@@ -128,6 +138,24 @@ __global__ void k_pairdata(const PairHdr *__restrict__ hdr, const int32_t *__res
             out[r++] = p;
         }
     }
+}
+
+__global__ void k_to_f32(const PrimRec *__restrict__ in, int64_t n, PrimRec32 *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const PrimRec r = in[t];
+    PrimRec32 o;
+    o.z = (float)r.z;
+    o.i2z = (float)r.i2z;
+    o.Px = (float)r.Px;
+    o.Py = (float)r.Py;
+    o.Pz = (float)r.Pz;
+    o.PAx = (float)r.PAx;
+    o.PAy = (float)r.PAy;
+    o.PAz = (float)r.PAz;
+    o.K = (float)r.K;
+    o.B = (float)r.B;
+    out[t] = o;
 }
 
 __global__ void k_fill(double *K, int64_t n, int64_t ld) {
@@ -187,6 +215,9 @@ __global__ void k_asym(const double *P, int64_t n, int64_t ld, double *part) {
                          const double *, double *, hipStream_t);
 HFX_FOR_CLASSES(DECL)
 #undef DECL
+#define DECL32(T) void launch_eri32_##T(const QuartetArgs &, unsigned, hipStream_t);
+HFX_FOR_CLASSES(DECL32)
+#undef DECL32
 void launch_schwarz_00(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
 void launch_schwarz_10(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
 void launch_schwarz_11(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
@@ -209,6 +240,11 @@ typedef void (*schwarz_fn)(const PairHdr *, const PrimRec *, const int32_t *, in
 // class index cb(cb+1)/2 + ck, pair classes ss ps pp ds dp dd
 static const eri_fn k_eri_tab[21] = {
 #define E(T) launch_eri_##T,
+    HFX_FOR_CLASSES(E)
+#undef E
+};
+static const eri_fn k_eri32_tab[21] = {
+#define E(T) launch_eri32_##T,
     HFX_FOR_CLASSES(E)
 #undef E
 };
@@ -397,9 +433,11 @@ extern "C" hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, co
     cleanup();
     if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("pair data: ") + hipGetErrorString(e));
     const double *tab = nullptr;
-    hfx_status s = boys_table(&tab);
+    const float *tab32 = nullptr;
+    hfx_status s = boys_table(&tab, &tab32);
     if (s != HFX_OK) return s;
     P->d_boys = tab;
+    P->d_boys32 = tab32;
     *out = P.release();
     return HFX_OK;
 }
@@ -408,6 +446,7 @@ hfx_pairs_s::~hfx_pairs_s() {
     hipFree(d_hdr);
     hipFree(d_prim);
     hipFree(d_Q);
+    hipFree(d_prim32);
     drop_lists();
     hipFree(d_count);
 }
@@ -462,6 +501,22 @@ hfx_status compute_bounds(hfx_pairs p, const hfx_opts *o, hipStream_t st) {
     p->have_Q = true;
     p->q_op = op;
     p->q_om2 = om2;
+    p->prim32_valid = false;
+    return HFX_OK;
+}
+
+// FP32 copies of the (sorted) primitive records, made on first mixed build.
+hfx_status ensure_prim32(hfx_pairs p, hipStream_t st) {
+    if (p->prim32_valid) return HFX_OK;
+    if (!p->d_prim32) {
+        if (hipMalloc(&p->d_prim32, std::max<int64_t>(p->nrec, 1) * sizeof(PrimRec32)) != hipSuccess)
+            return fail(HFX_ENOMEM, "device allocation of FP32 records failed");
+        p->dev_bytes += p->nrec * sizeof(PrimRec32);
+    }
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((p->nrec + 255) / 256)), dim3(256), 0, st, p->d_prim, p->nrec,
+                       p->d_prim32);
+    HIPCHK(hipGetLastError());
+    p->prim32_valid = true;
     return HFX_OK;
 }
 
@@ -551,6 +606,8 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
                           hipStream_t st, unsigned long long *count, int shard, int nshards,
                           hipEvent_t *ev) {
     const int op = kernel_op(o);
+    const bool mixed = (o->prec == HFX_PREC_MIXED);
+    const double inf = HUGE_VAL;
     for (int cb = 0; cb < 6; ++cb)
         for (int ck = 0; ck <= cb; ++ck) {
             const ClassList &B = p->lists[cb], &Kl = p->lists[ck];
@@ -560,6 +617,7 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             QuartetArgs a;
             a.hdr = p->d_hdr;
             a.prim = p->d_prim;
+            a.prim32 = p->d_prim32;
             a.bra_ids = B.d_ids;
             a.bra_Q = B.d_Q;
             a.bra_grp = B.d_grp;
@@ -572,19 +630,30 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             a.ket_gnp = Kl.d_gnp;
             a.n_kgrp = Kl.ngrp;
             a.same = (cb == ck);
-            a.tau = o->tau;
             a.op = op;
             a.om2 = op ? o->omega * o->omega : 0.0;
             a.prim_tau = o->prim_tau;
             a.boys = p->d_boys;
+            a.boys32 = p->d_boys32;
             a.P = P;
             a.K = K;
             a.ld = ld;
-            a.count = count ? count + 2 * ci : nullptr;
             const int64_t nblk = (int64_t)((B.n - shard + nshards - 1) / nshards) * Kl.ngrp;
-            if (nblk > INT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
+            if (nblk * 16 > INT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
+            // FP64: Q_p Q_q >= max(tau, cut) in mixed mode, >= tau otherwise
+            a.tau = mixed ? std::max(o->tau, o->mixed_cut) : o->tau;
+            a.tau_hi = inf;
+            a.count = count ? count + 4 * ci : nullptr;
             k_eri_tab[ci](a, (unsigned)nblk, st);
             HIPCHK(hipGetLastError());
+            if (mixed && o->mixed_cut > o->tau) {
+                // FP32: tau <= Q_p Q_q < cut
+                a.tau = o->tau;
+                a.tau_hi = o->mixed_cut;
+                a.count = count ? count + 4 * ci + 2 : nullptr;
+                k_eri32_tab[ci](a, (unsigned)nblk, st);
+                HIPCHK(hipGetLastError());
+            }
         }
     if (ev) HIPCHK(hipEventRecord(ev[HFX_NCLASS], st));
     return HFX_OK;
@@ -621,9 +690,13 @@ static hfx_status build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, 
     if (s != HFX_OK) return s;
     s = build_lists(p, o->tau, st);
     if (s != HFX_OK) return s;
-    if (!p->d_count) HIPCHK(hipMalloc(&p->d_count, 2 * HFX_NCLASS * sizeof(unsigned long long)));
+    if (o->prec == HFX_PREC_MIXED) {
+        s = ensure_prim32(p, st);
+        if (s != HFX_OK) return s;
+    }
+    if (!p->d_count) HIPCHK(hipMalloc(&p->d_count, 4 * HFX_NCLASS * sizeof(unsigned long long)));
     unsigned long long *cnt = st_out ? p->d_count : nullptr;
-    if (cnt) hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, cnt, 2 * HFX_NCLASS);
+    if (cnt) hipLaunchKernelGGL(k_fill_u64, dim3(2), dim3(64), 0, st, cnt, 4 * HFX_NCLASS);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, K_dev, n, ld);
     HIPCHK(hipGetLastError());
     hipEvent_t ev[HFX_NCLASS + 1] = {};
@@ -635,7 +708,7 @@ static hfx_status build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, 
     hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(16, 16), 0, st, K_dev, n, ld);
     HIPCHK(hipGetLastError());
     if (st_out) {
-        std::vector<unsigned long long> h(2 * HFX_NCLASS);
+        std::vector<unsigned long long> h(4 * HFX_NCLASS);
         HIPCHK(hipMemcpyAsync(h.data(), cnt, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         std::memset(st_out, 0, sizeof(*st_out));
@@ -651,11 +724,12 @@ static hfx_status build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, 
             float cm = 0.f;
             HIPCHK(hipEventElapsedTime(&cm, ev[c], ev[c + 1]));
             st_out->class_device_s[c] = cm * 1e-3;
-            st_out->class_quartets[c] = (int64_t)h[2 * c];
-            st_out->class_flops[c] = (mv[c] + model_prim_overhead(kernel_op(o), L)) * (double)h[2 * c + 1] +
-                                     mp[c] * (double)h[2 * c];
-            st_out->quartets += (int64_t)h[2 * c];
-            st_out->prim_quartets += (int64_t)h[2 * c + 1];
+            const double nq = (double)(h[4 * c] + h[4 * c + 2]), npq = (double)(h[4 * c + 1] + h[4 * c + 3]);
+            st_out->class_quartets[c] = (int64_t)(h[4 * c] + h[4 * c + 2]);
+            st_out->class_flops[c] = (mv[c] + model_prim_overhead(kernel_op(o), L)) * npq + mp[c] * nq;
+            st_out->quartets += st_out->class_quartets[c];
+            st_out->quartets_fp32 += (int64_t)h[4 * c + 2];
+            st_out->prim_quartets += (int64_t)npq;
             st_out->flops += st_out->class_flops[c];
         }
         for (auto &e : ev) hipEventDestroy(e);

@@ -39,6 +39,9 @@ struct hfx_pairs_s {
     hfx::PrimRec *d_prim = nullptr;
     double *d_Q = nullptr;
     const double *d_boys = nullptr;
+    const float *d_boys32 = nullptr;
+    hfx::PrimRec32 *d_prim32 = nullptr;
+    bool prim32_valid = false;
     unsigned long long *d_count = nullptr;
     bool have_Q = false;
     int q_op = -1;
