@@ -49,6 +49,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--mixed-cut", type=float, default=1e-6, help="tuned FP32 cut on Q_IJ Q_KL")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
+    ap.add_argument("--batch-natom", type=str, default="6,20",
+                    help="atom-count range of the batched systems (scaled-down config-3 recipe)")
+    ap.add_argument("--serve-natom", type=str, default="6,24",
+                    help="atom-count range of served requests (scaled-down config-4 recipe)")
+    ap.add_argument("--serve-requests", type=int, default=12)
     return ap.parse_args()
 
 
@@ -63,7 +70,7 @@ def cpu_baseline(sysm, tau, omega, budget_s):
     rng = np.random.default_rng(12345)
     npair = sysm.nshell * (sysm.nshell + 1) // 2
     cores = len(os.sched_getaffinity(0))
-    pool = np.unique(rng.integers(0, npair, size=min(npair, 700)))
+    pool = np.unique(rng.integers(0, npair, size=min(npair, 2400)))
     qpool = oracle.schwarz_list(sysm, pool, omega=omega)
     ii, jj = np.tril_indices(len(pool))
     keep = qpool[ii] * qpool[jj] >= tau
@@ -82,6 +89,116 @@ def cpu_baseline(sysm, tau, omega, budget_s):
             f"among a seeded random pool of {len(pool)} shell pairs of the same system; FP64 integrals and "
             f"digestion into K; {dt:.1f} s")
     return {"value": n / dt, "unit": "quartets/s", "cores": cores, "kind": "oracle", "sample": desc}
+
+
+def batch_leg(a, hfx, hi, torch):
+    """64 independent systems (config-3 recipe: uniform atom counts, l_max in
+    {1, 2}, config-1 shells and P) in one persistent launch per class through
+    the device work queue, FP64 and mixed, against building them one by one."""
+    lo, hi_ = (int(x) for x in a.batch_natom.split(","))
+    systems = hi.config3(seed=3, nsys=64, natom_range=(lo, hi_))
+    tau, omega = 1e-10, hi.OMEGA_HSE
+    res = {"workload": f"64 systems, atoms uniform in [{lo},{hi_}] (config-3 recipe scaled down from [20,400]), "
+                       f"l_max in {{1,2}}, erfc omega={omega}, tau={tau}"}
+    for name, prec in (("fp64", hfx.PREC_FP64), ("mixed", hfx.PREC_MIXED)):
+        o = hfx.opts(tau=tau, omega=omega, prec=prec, mixed_cut=a.mixed_cut)
+        pairs = [hfx.pairs_from_system(s, o) for s in systems]
+        Ps = [torch.from_numpy(s.P).cuda() for s in systems]
+        Ks = [torch.empty_like(P) for P in Ps]
+        t0 = time.perf_counter()
+        hfx.build_K_batch(pairs, Ps, Ks, o)  # first call: bounds, lists, autotuning
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        st = hfx.build_K_batch(pairs, Ps, Ks, o, stats=True)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        Kb = [K.cpu().numpy() for K in Ks]
+        # the same systems one call at a time (lists already resident)
+        t0 = time.perf_counter()
+        for p, P, K in zip(pairs, Ps, Ks):
+            hfx.build_K(p, P, K, o)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        dmax = max(float(np.abs(K.cpu().numpy() - k).max()) for K, k in zip(Ks, Kb))
+        res[name] = {"value": st["quartets"] / tb, "unit": "quartets/s", "batch_s": tb,
+                     "sequential_s": ts, "speedup_vs_sequential": ts / tb, "first_call_s": t_first,
+                     "quartets": st["quartets"], "max_abs_dK_batch_vs_solo": dmax}
+        print(f"# batch {name}: {tb:.3f} s vs sequential {ts:.3f} s", file=sys.stderr, flush=True)
+    return res
+
+
+def serve_leg(a, hfx, hi, torch):
+    """Served K-builds (config-4 recipe scaled down): requests with log-uniform
+    atom counts, each 10 SCF-like iterations with P perturbed by 1e-3 relative
+    noise, Poisson arrivals at 70 % of the measured closed-loop capacity,
+    mixed precision, pair data resident, admission by an HBM budget."""
+    lo, hi_ = (int(x) for x in a.serve_natom.split(","))
+    reqs = hi.served_requests(seed=4, nreq=a.serve_requests, natom_range=(lo, hi_), iters=10)
+    tau, omega = 1e-10, hi.OMEGA_HSE
+    o = hfx.opts(tau=tau, omega=omega, prec=hfx.PREC_MIXED, mixed_cut=a.mixed_cut)
+    systems = [hi.lattice_system(r["natom"], seed=r["seed"], name=f"served{r['id']}") for r in reqs]
+    pairs = [hfx.pairs_from_system(s, o) for s in systems]
+    Ps = [torch.from_numpy(s.P).cuda() for s in systems]
+    Ks = [torch.empty_like(P) for P in Ps]
+    budget = int(32 * 2**30)
+    srv = hfx.Server(budget, max_inflight=4)
+    rng = np.random.default_rng(44)
+
+    def run(arrivals):
+        """arrivals[i] = release time of request i (s); each request runs its
+        iterations back to back; returns per-build and per-request latencies."""
+        t_start = time.perf_counter()
+        state = [{"it": 0, "ticket": None, "t_req": None} for _ in reqs]
+        build_lat, req_lat, quartets = [], [], 0
+        left = len(reqs)
+        while left:
+            now = time.perf_counter() - t_start
+            for i, stt in enumerate(state):
+                if stt["it"] >= reqs[i]["iters"]:
+                    continue
+                if stt["ticket"] is None and now >= arrivals[i]:
+                    if stt["t_req"] is None:
+                        stt["t_req"] = time.perf_counter()
+                    Pn = hi.perturbed_density(systems[i].P, rng)
+                    Ps[i].copy_(torch.from_numpy(Pn))
+                    torch.cuda.synchronize()
+                    stt["ticket"] = srv.submit(pairs[i], Ps[i], Ks[i], o)
+                elif stt["ticket"] is not None:
+                    done, st = srv.poll(stt["ticket"])
+                    if done:
+                        build_lat.append(st["latency_s"])
+                        quartets += st["quartets"]
+                        stt["ticket"] = None
+                        stt["it"] += 1
+                        if stt["it"] == reqs[i]["iters"]:
+                            req_lat.append(time.perf_counter() - stt["t_req"])
+                            left -= 1
+            time.sleep(0.0005)
+        return time.perf_counter() - t_start, build_lat, req_lat, quartets
+
+    # capacity: closed loop, everything released at t = 0
+    wall, bl, rl, nq = run([0.0] * len(reqs))
+    cap = len(reqs) / wall  # requests/s
+    lam = 0.7 * cap
+    arr = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+    arr -= arr[0]
+    wall2, bl2, rl2, nq2 = run(list(arr))
+    pct = lambda v, q: float(np.percentile(v, q))
+    return {
+        "workload": f"{len(reqs)} requests, atoms log-uniform in [{lo},{hi_}] (config-4 recipe scaled down from "
+                    f"[50,2000]), 10 iterations each, P x (1 + 1e-3 E_t), mixed cut {a.mixed_cut}, "
+                    f"HBM budget {budget >> 30} GiB, 4 in flight",
+        "capacity_req_per_s": cap,
+        "lambda_req_per_s": lam,
+        "value": nq2 / wall2,
+        "unit": "quartets/s",
+        "build_p50_ms": 1e3 * pct(bl2, 50),
+        "build_p99_ms": 1e3 * pct(bl2, 99),
+        "request_p50_s": pct(rl2, 50),
+        "request_p99_s": pct(rl2, 99),
+        "closed_loop_quartets_per_s": nq / wall,
+    }
 
 
 def main():
@@ -197,6 +314,11 @@ def main():
             "max_abs_dK_vs_fp64_gpu": float(np.abs(Kmh - Kh).max()),
             "trPK_err_vs_fp64_gpu": float(abs(np.sum(Ph * Kmh) - np.sum(Ph * Kh))),
         }
+    if not a.no_batch:
+        out["batched"] = batch_leg(a, hfx, hi, torch)
+    if not a.no_serve:
+        out["served"] = serve_leg(a, hfx, hi, torch)
+        print("# served leg done", file=sys.stderr, flush=True)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sysm, tau, omega, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -568,6 +568,11 @@ def generate(outdir, T="double", splits=None):
                 f"void launch_eri32_{tag}(const QuartetArgs &a, unsigned nblk, hipStream_t s) {{",
                 f"  hipLaunchKernelGGL(k_eri32<{nm}>, dim3(nblk * {nm}::NSPLIT), dim3(64), 0, s, a);",
                 "}",
+                f"void launch_persist32_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
+                "                          unsigned grid, hipStream_t s) {",
+                f"  hipLaunchKernelGGL(k_eri32_persist<{nm}>, dim3(grid), dim3(64), 0, s, j, nj, vt, h, claim);",
+                "}",
+                f"int nsplit32_{tag}() {{ return {nm}::NSPLIT; }}",
             ]
             tu.append("}  // namespace hfx")
             with open(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "w") as f:
@@ -581,6 +586,11 @@ def generate(outdir, T="double", splits=None):
             f"void launch_eri_{tag}(const QuartetArgs &a, unsigned nblk, hipStream_t s) {{",
             f"  hipLaunchKernelGGL(k_eri<{nm}>, dim3(nblk * {nm}::NSPLIT), dim3(64), 0, s, a);",
             "}",
+            f"void launch_persist_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
+            "                        unsigned grid, hipStream_t s) {",
+            f"  hipLaunchKernelGGL(k_eri_persist<{nm}>, dim3(grid), dim3(64), 0, s, j, nj, vt, h, claim);",
+            "}",
+            f"int nsplit_{tag}() {{ return {nm}::NSPLIT; }}",
             f"void launch_eval_{tag}(const PairHdr *h, const PrimRec *p, const int32_t *bk, int n, int op,",
             "                    double om2, const double *tab, double *out, hipStream_t s) {",
             f"  hipLaunchKernelGGL(k_eval<{nm}>, dim3((n + 63) / 64), dim3(64), 0, s, h, p, bk, n, op, om2, tab, out);",

@@ -484,6 +484,68 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     tile_dispatch32<C, 0>(a, w, p, g, lo, cut);
 }
 
+// ----------------------------------------------------------------------
+// Persistent launch over many systems: a device work queue.  Every job is one
+// system's class pair (its QuartetArgs); its virtual blocks are
+// (bra slot, ket group, ket sub-range, slice), numbered from vbase.  A fixed
+// grid of workgroups pops `claim` virtual blocks at a time from an atomic
+// head until the queue is drained (every wave reaches the exit once the head
+// passes vtotal).  tq = ket quartets per sub-range (the quartet-block size).
+struct BatchJob {
+    QuartetArgs a;
+    long long vbase;
+    int nsub;
+    int tq;
+};
+
+template <class C, bool F32>
+__device__ __forceinline__ void persist_loop(const BatchJob *__restrict__ jobs, int njobs, long long vtotal,
+                                             unsigned long long *head, int claim) {
+    for (;;) {
+        unsigned long long v0 = 0;
+        if (threadIdx.x == 0) v0 = atomicAdd(head, (unsigned long long)claim);
+        v0 = __shfl(v0, 0);
+        if ((long long)v0 >= vtotal) break;
+        const long long vend = min((long long)v0 + claim, vtotal);
+        for (long long v = (long long)v0; v < vend; ++v) {
+            int lo_j = 0, hi_j = njobs;  // last job with vbase <= v
+            while (hi_j - lo_j > 1) {
+                const int m = (lo_j + hi_j) >> 1;
+                if (jobs[m].vbase <= v) lo_j = m;
+                else hi_j = m;
+            }
+            const BatchJob &J = jobs[lo_j];
+            long long r = v - J.vbase;
+            const int w = (int)(r % C::NSPLIT);
+            r /= C::NSPLIT;
+            const int sub = (int)(r % J.nsub);
+            r /= J.nsub;
+            const int g = (int)(r % J.a.n_kgrp);
+            const int p = J.a.bra_first + (int)(r / J.a.n_kgrp) * J.a.bra_stride;
+            int lo = 0;
+            const int cut = ket_cut(J.a, p, g, &lo);
+            const int lo2 = lo + sub * J.tq;
+            const int cut2 = min(cut, lo2 + J.tq);
+            if (cut2 <= lo2) continue;
+            if (w == 0 && threadIdx.x == 0 && J.a.count) atomicAdd(&J.a.count[0], (unsigned long long)(cut2 - lo2));
+            if constexpr (F32) tile_dispatch32<C, 0>(J.a, w, p, g, lo2, cut2);
+            else tile_dispatch<C, 0>(J.a, w, p, g, lo2, cut2);
+        }
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri_persist(
+    const BatchJob *__restrict__ jobs, int njobs, long long vtotal, unsigned long long *head, int claim) {
+    persist_loop<C, false>(jobs, njobs, vtotal, head, claim);
+}
+
+template <class C>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri32_persist(
+    const BatchJob *__restrict__ jobs, int njobs, long long vtotal, unsigned long long *head, int claim) {
+    persist_loop<C, true>(jobs, njobs, vtotal, head, claim);
+}
+
 // Schwarz factor of each pair of one pair class: Q = sqrt(max diagonal (ij|ij)).
 template <class C>
 __global__ __launch_bounds__(64) void k_schwarz(const PairHdr *__restrict__ hdr,

@@ -169,6 +169,17 @@ __global__ void k_fill_u64(unsigned long long *c, int n) {
     if (t < n) c[t] = 0ull;
 }
 
+void launch_fill_K(double *K, int64_t n, int64_t ld, hipStream_t st);
+void launch_fill_u64(unsigned long long *c, int n, hipStream_t st);
+void launch_symmetrize(double *K, int64_t n, int64_t ld, hipStream_t st);
+
+void launch_fill_K(double *K, int64_t n, int64_t ld, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, K, n, ld);
+}
+void launch_fill_u64(unsigned long long *c, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, c, n);
+}
+
 // K = K' + K'^T in place; one thread per (i, j) with j >= i.
 __global__ void k_symmetrize(double *K, int64_t n, int64_t ld) {
     const int64_t i = (int64_t)blockIdx.y * 16 + threadIdx.y;
@@ -177,6 +188,11 @@ __global__ void k_symmetrize(double *K, int64_t n, int64_t ld) {
     const double s = K[i * ld + j] + K[j * ld + i];
     K[i * ld + j] = s;
     K[j * ld + i] = s;
+}
+
+void launch_symmetrize(double *K, int64_t n, int64_t ld, hipStream_t st) {
+    const unsigned g = (unsigned)((n + 15) / 16);
+    hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(16, 16), 0, st, K, n, ld);
 }
 
 // Per-block max |P_ij - P_ji| and max |P_ij|.
@@ -285,7 +301,7 @@ static void nrm_coefs(const std::vector<hfx_shell> &sh, const double *exps, cons
     }
 }
 
-static hfx_status check_opts(const hfx_opts *o) {
+hfx_status check_opts(const hfx_opts *o) {
     if (!o) return fail(HFX_EINVAL, "opts is NULL");
     if (!(o->tau >= 0.0) || !std::isfinite(o->tau)) return fail(HFX_EINVAL, "tau must be finite and >= 0");
     if (o->op != HFX_OP_COULOMB && o->op != HFX_OP_ERFC) return fail(HFX_EINVAL, "unknown operator");
@@ -671,8 +687,8 @@ extern "C" hfx_status hfx_schwarz_bounds(hfx_pairs p, const hfx_opts *o, double 
     return HFX_OK;
 }
 
-static hfx_status build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
-                               const hfx_opts *o, int shard, int nshards, void *stream, hfx_stats *st_out) {
+hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
+                             const hfx_opts *o, int shard, int nshards, void *stream, hfx_stats *st_out) {
     auto t0 = std::chrono::steady_clock::now();
     if (!p) return fail(HFX_EINVAL, "pairs is NULL");
     if (!P_dev || !K_dev) return fail(HFX_EINVAL, "P or K is NULL");

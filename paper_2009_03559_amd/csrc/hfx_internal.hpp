@@ -22,8 +22,24 @@ struct ClassList {
 hfx_status fail(hfx_status s, const std::string &msg);
 int kernel_op(const hfx_opts *o);
 extern const int PAIR_L[6][2];
+hfx_status check_opts(const hfx_opts *o);
+hfx_status check_P(const double *P, int64_t n, int64_t ld, hipStream_t st);
+hfx_status compute_bounds(hfx_pairs p, const hfx_opts *o, hipStream_t st);
+hfx_status build_lists(hfx_pairs p, double tau, hipStream_t st);
+hfx_status ensure_prim32(hfx_pairs p, hipStream_t st);
+hfx_status build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld, const hfx_opts *o,
+                        int shard, int nshards, void *stream, hfx_stats *st_out);
+void launch_fill_K(double *K, int64_t n, int64_t ld, hipStream_t st);
+void launch_fill_u64(unsigned long long *c, int n, hipStream_t st);
+void launch_symmetrize(double *K, int64_t n, int64_t ld, hipStream_t st);
+const double *model_vrr();
+const double *model_post();
+double model_prim_overhead(int op, int L);
 
 }  // namespace hfx
+
+struct hfx_pairs_s;
+typedef struct hfx_pairs_s *hfx_pairs;
 
 struct hfx_pairs_s {
     int natom = 0, nshell = 0;

@@ -1,0 +1,163 @@
+"""Batched persistent launch (device work queue + autotuner) and the
+continuous-batching server: every system's K is the same alone, in a batch
+and in the served mix (FP64 atomics only change the summation order, so the
+bar is 1e-12 hartree), and matches the oracle on small systems."""
+
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import hfx_inputs as hi
+import oracle
+import paper_2009_03559_amd as hfx
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device(tmp_path_factory):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    os.environ["HFX_TUNE_CACHE"] = str(tmp_path_factory.mktemp("tune") / "autotune.txt")
+
+
+def _systems(n=5, seed=40):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        natom = int(rng.integers(2, 7))
+        lmax = int(rng.integers(1, 3))
+        out.append(hi.lattice_system(natom, seed=seed + i, lmax=lmax, nprim_range=(1, 3)))
+    return out
+
+
+def _solo(s, o):
+    p = hfx.pairs_from_system(s, o)
+    P = torch.from_numpy(s.P).cuda()
+    K = torch.empty_like(P)
+    st = hfx.build_K(p, P, K, o, stats=True)
+    torch.cuda.synchronize()
+    return K.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("prec", [hfx.PREC_FP64, hfx.PREC_MIXED])
+def test_batch_equals_solo_and_oracle(prec):
+    systems = _systems()
+    o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE, prec=prec)
+    pairs = [hfx.pairs_from_system(s, o) for s in systems]
+    Ps = [torch.from_numpy(s.P).cuda() for s in systems]
+    Ks = [torch.empty_like(P) for P in Ps]
+    _say("batch", [s.natom for s in systems], "prec", prec)
+    st = hfx.build_K_batch(pairs, Ps, Ks, o, stats=True)
+    torch.cuda.synchronize()
+    nq = 0
+    for s, K in zip(systems, Ks):
+        Ksolo, sts = _solo(s, o)
+        Kb = K.cpu().numpy()
+        assert np.abs(Kb - Ksolo).max() <= 1e-12, np.abs(Kb - Ksolo).max()
+        nq += sts["quartets"]
+        if prec == hfx.PREC_FP64:
+            Ko, _, _ = oracle.build_K(s, tau=1e-10, omega=hi.OMEGA_HSE)
+            assert np.abs(Kb - Ko).max() <= 1e-10
+    assert st["quartets"] == nq
+    # a second call reuses the tuned parameters and the resident lists
+    st2 = hfx.build_K_batch(pairs, Ps, Ks, o, stats=True)
+    assert st2["quartets"] == nq
+
+
+def test_batch_rejects_duplicate_handle():
+    s = hi.config0()
+    o = hfx.opts(omega=0.11)
+    p = hfx.pairs_from_system(s, o)
+    P = torch.from_numpy(s.P).cuda()
+    K1, K2 = torch.empty_like(P), torch.empty_like(P)
+    with pytest.raises(hfx.HfxError) as e:
+        hfx.build_K_batch([p, p], [P, P], [K1, K2], o)
+    assert e.value.status == hfx.HFX_EINVAL
+
+
+def test_batch_empty():
+    assert hfx.build_K_batch([], [], [], hfx.opts(), stats=True)["quartets"] == 0
+
+
+def test_served_equals_solo_in_mix():
+    """Requests of several systems, three SCF-like iterations each with a
+    perturbed P, submitted together: four workers run them concurrently; each
+    K equals the system's K built alone."""
+    systems = _systems(n=6, seed=50)
+    o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
+    pairs = [hfx.pairs_from_system(s, o) for s in systems]
+    srv = hfx.Server(hbm_budget_bytes=1 << 34, max_inflight=4)
+    rng = np.random.default_rng(3)
+    jobs = []
+    for it in range(3):
+        for i, s in enumerate(systems):
+            Pn = hi.perturbed_density(s.P, rng)
+            P = torch.from_numpy(Pn).cuda()
+            K = torch.empty_like(P)
+            torch.cuda.synchronize()
+            t = srv.submit(pairs[i], P, K, o)
+            jobs.append((i, Pn, P, K, t))
+    done = {}
+    t_end = time.time() + 120
+    while len(done) < len(jobs) and time.time() < t_end:
+        for (i, Pn, P, K, t) in jobs:
+            if t in done:
+                continue
+            ok, st = srv.poll(t)
+            if ok:
+                done[t] = st
+        time.sleep(0.01)
+    assert len(done) == len(jobs)
+    lat = sorted(st["latency_s"] for st in done.values())
+    _say("served", len(jobs), "requests; p50 %.3f s p99 %.3f s" % (np.percentile(lat, 50), np.percentile(lat, 99)))
+    for (i, Pn, P, K, t) in jobs:
+        s = systems[i]
+        Ps = torch.from_numpy(Pn).cuda()
+        Kref = torch.empty_like(Ps)
+        ps = hfx.pairs_from_system(s, o)
+        hfx.build_K(ps, Ps, Kref, o)
+        torch.cuda.synchronize()
+        assert torch.abs(K - Kref).max().item() <= 1e-12
+    with pytest.raises(hfx.HfxError) as e:
+        srv.poll(jobs[0][4])  # already collected
+    assert e.value.status == hfx.HFX_ENOTFOUND
+
+
+def test_server_admission_and_errors():
+    s = hi.config0()
+    o = hfx.opts(omega=0.11)
+    p = hfx.pairs_from_system(s, o)
+    P = torch.from_numpy(s.P).cuda()
+    K = torch.empty_like(P)
+    small = hfx.Server(hbm_budget_bytes=1024, max_inflight=2)
+    with pytest.raises(hfx.HfxError) as e:
+        small.submit(p, P, K, o)
+    assert e.value.status == hfx.HFX_ENOMEM
+    with pytest.raises(hfx.HfxError) as e:
+        small.poll(12345)
+    assert e.value.status == hfx.HFX_ENOTFOUND
+    # a budget that fits one request at a time still serves all of them
+    one = hfx.Server(hbm_budget_bytes=p.device_bytes + 2 * 8 * s.nbf * s.nbf + 64, max_inflight=3)
+    q = [hfx.pairs_from_system(s, o) for _ in range(3)]
+    Ks = [torch.empty_like(P) for _ in range(3)]
+    ts = [one.submit(q[i], P, Ks[i], o) for i in range(3)]
+    t_end = time.time() + 60
+    pend = set(ts)
+    while pend and time.time() < t_end:
+        for t in list(pend):
+            if one.poll(t)[0]:
+                pend.discard(t)
+        time.sleep(0.01)
+    assert not pend
+    for i in range(1, 3):
+        assert torch.abs(Ks[i] - Ks[0]).max().item() <= 1e-12
