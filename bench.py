@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--serve-natom", type=str, default="6,24",
                     help="atom-count range of served requests (scaled-down config-4 recipe)")
     ap.add_argument("--serve-requests", type=int, default=12)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 512 MiB device copy five times (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -201,8 +203,50 @@ def serve_leg(a, hfx, hi, torch):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dominant_kernel.json")
+
+
+def source_hash():
+    """Hash of the sources the quartet kernels are generated and compiled from;
+    stored HBM-traffic counters apply only while it is unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hfx_device.hpp", "gen_eri.py"):
+        with open(os.path.join(ROOT, "paper_2009_03559_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_tag, shards):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None
+    if the kernels changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash() or t.get("kernel_tag") != kernel_tag or t.get("shards") != shards:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def copy_calibration():
+    import torch
+    n = (512 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8, "launches": 5}))
+
+
 def main():
     a = parse()
+    if a.copy_calib:
+        copy_calibration()
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported in this build "
               "(the multi-GPU split is hfx_build_K_shard + one all-reduce of K)", file=sys.stderr)
@@ -288,7 +332,7 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": traffic_for(hfx.CLASS_TAGS[ci], a.shards),
         },
     }
     if not a.no_mixed:

@@ -13,7 +13,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "libhfx.so")
+LIB_PATH = os.environ.get("HFX_LIB") or os.path.join(_HERE, "_build", "libhfx.so")
 
 HFX_OK, HFX_EINVAL, HFX_EUNSUPPORTED, HFX_ENOMEM, HFX_EBUSY, HFX_ENOTFOUND, HFX_EDEVICE, HFX_EASYM = range(8)
 STATUS_NAMES = ["OK", "EINVAL", "EUNSUPPORTED", "ENOMEM", "EBUSY", "ENOTFOUND", "EDEVICE", "EASYM"]

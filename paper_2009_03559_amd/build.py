@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(HERE, "_build")
+BUILD = os.environ.get("HFX_BUILD_DIR") or os.path.join(HERE, "_build")
 GEN = os.path.join(BUILD, "gen")
 OBJ = os.path.join(BUILD, "obj")
 LIB = os.path.join(BUILD, "libhfx.so")

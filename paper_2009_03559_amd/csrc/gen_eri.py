@@ -481,11 +481,18 @@ def split_f(lc, ld, G):
 PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 
 # Number of ket slices (waves) per quartet for the classes whose contracted
-# array does not fit one lane's registers.
+# array does not fit one lane's registers.  Measured on the 256-atom DZP
+# shard: more slices than these slow the mid classes (recomputed shared
+# recurrence), fewer spill registers in the high classes.
 DEFAULT_SPLITS = {
     (2, 1, 1, 1): 2, (2, 1, 2, 0): 2, (2, 2, 1, 0): 2, (2, 2, 2, 0): 4,
-    (2, 1, 2, 1): 4, (2, 2, 1, 1): 4, (2, 2, 2, 1): 8, (2, 2, 2, 2): 16,
+    (2, 1, 2, 1): 4, (2, 2, 1, 1): 4, (2, 2, 2, 1): 16, (2, 2, 2, 2): 31,
 }
+
+# Override for tuning: HFX_SPLITS="2221:16,2222:32".
+for _kv in filter(None, os.environ.get("HFX_SPLITS", "").split(",")):
+    _k, _v = _kv.split(":")
+    DEFAULT_SPLITS[tuple(int(c) for c in _k)] = int(_v)
 
 # FP32 slices: the same as FP64 (fewer slices spill in FP32 too).
 DEFAULT_SPLITS_F32 = dict(DEFAULT_SPLITS)
@@ -522,7 +529,7 @@ def generate(outdir, T="double", splits=None):
         nsph = (2 * la + 1) * (2 * lb + 1) * (2 * lc + 1) * (2 * ld + 1)
         em.lines.append(f"  static constexpr int NOUT = {nsph};")
         _, vflops = emit_vrr(em, la, lb, lc, ld, "vrr")
-        G = splits.get((la, lb, lc, ld), 1)
+        G = min(splits.get((la, lb, lc, ld), 1), NF)  # no empty slices
         em.lines.append(f"  static constexpr int NSPLIT = {G};")
         em.lines.append(f"  static constexpr int WAVES = {WAVES.get((la, lb, lc, ld), 1)};")
         split_cost = []
@@ -565,8 +572,12 @@ def generate(outdir, T="double", splits=None):
                 '#include "hfx_device.hpp"',
                 f'#include "eri_{tag}{suffix}.h"',
                 "namespace hfx {",
-                f"void launch_eri32_{tag}(const QuartetArgs &a, unsigned nblk, hipStream_t s) {{",
-                f"  hipLaunchKernelGGL(k_eri32<{nm}>, dim3(nblk * {nm}::NSPLIT), dim3(64), 0, s, a);",
+                f"void launch_eri32_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
+                "  QuartetArgs a = a0;",
+                f"  a.nblk = (int)(nblk * {nm}::NSPLIT);",
+                f"  const unsigned span = 64u * {nm}::NSPLIT;  // 8 XCDs x chunk",
+                "  const unsigned grid = ((unsigned)a.nblk + span - 1) / span * span;",
+                f"  hipLaunchKernelGGL(k_eri32<{nm}>, dim3(grid), dim3(64), 0, s, a);",
                 "}",
                 f"void launch_persist32_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
                 "                          unsigned grid, hipStream_t s) {",
@@ -583,8 +594,12 @@ def generate(outdir, T="double", splits=None):
             '#include "hfx_device.hpp"',
             f'#include "eri_{tag}{suffix}.h"',
             "namespace hfx {",
-            f"void launch_eri_{tag}(const QuartetArgs &a, unsigned nblk, hipStream_t s) {{",
-            f"  hipLaunchKernelGGL(k_eri<{nm}>, dim3(nblk * {nm}::NSPLIT), dim3(64), 0, s, a);",
+            f"void launch_eri_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
+            "  QuartetArgs a = a0;",
+            f"  a.nblk = (int)(nblk * {nm}::NSPLIT);",
+            f"  const unsigned span = 64u * {nm}::NSPLIT;  // 8 XCDs x chunk",
+            "  const unsigned grid = ((unsigned)a.nblk + span - 1) / span * span;",
+            f"  hipLaunchKernelGGL(k_eri<{nm}>, dim3(grid), dim3(64), 0, s, a);",
             "}",
             f"void launch_persist_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
             "                        unsigned grid, hipStream_t s) {",

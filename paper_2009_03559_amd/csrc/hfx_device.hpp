@@ -120,7 +120,7 @@ template <class C>
 __device__ __forceinline__ void prim_quartet(const PrimRec &b, double kz, double ki2z, double kPx,
                                              double kPy, double kPz, double kQCx, double kQCy,
                                              double kQCz, double kK, int op, double om2,
-                                             const double *__restrict__ tab, double *acc) {
+                                             const double *__restrict__ tab, double *acc, double om) {
     const double ze = b.z + kz;
     const double rs = rsqrt(ze);
     const double ize = rs * rs;
@@ -131,8 +131,7 @@ __device__ __forceinline__ void prim_quartet(const PrimRec &b, double kz, double
     double g[C::L + 1];
     boys<C::L>(T, tab, g);
     if (op) {
-        const double tr = rsqrt(om2 + rho);
-        const double th = sqrt(om2) * tr;   // theta
+        const double th = om * rsqrt(om2 + rho);  // theta
         const double th2 = th * th;
         double g2[C::L + 1];
         boys<C::L>(th2 * T, tab, g2);
@@ -155,7 +154,7 @@ template <class C, int W>
 __device__ __forceinline__ void prim_quartet_p(const PrimRec &b, double kz, double ki2z, double kPx,
                                              double kPy, double kPz, double kQCx, double kQCy,
                                              double kQCz, double kK, int op, double om2,
-                                             const double *__restrict__ tab, double *acc) {
+                                             const double *__restrict__ tab, double *acc, double om) {
     const double ze = b.z + kz;
     const double rs = rsqrt(ze);
     const double ize = rs * rs;
@@ -166,8 +165,7 @@ __device__ __forceinline__ void prim_quartet_p(const PrimRec &b, double kz, doub
     double g[C::L + 1];
     boys<C::L>(T, tab, g);
     if (op) {
-        const double tr = rsqrt(om2 + rho);
-        const double th = sqrt(om2) * tr;   // theta
+        const double th = om * rsqrt(om2 + rho);  // theta
         const double th2 = th * th;
         double g2[C::L + 1];
         boys<C::L>(th2 * T, tab, g2);
@@ -296,6 +294,10 @@ struct QuartetArgs {
     int32_t n_bra;
     int32_t bra_first;        // slots bra_first, bra_first + bra_stride, ... (sharding)
     int32_t bra_stride;
+    int32_t nsub;             // ket sub-ranges per (bra slot, ket group) block row
+    int32_t tq;               // ket quartets per sub-range
+    int32_t nblk;             // logical blocks (the grid is padded to a multiple of 8)
+    double om;                // omega
     const int32_t *ket_ids;   // ket class, same order
     const double *ket_Q;
     const int32_t *ket_goff;  // n_kgrp + 1 group offsets into the ket list
@@ -315,6 +317,19 @@ struct QuartetArgs {
     int64_t ld;
     unsigned long long *count;  // [0] quartets, [1] primitive quartets of this launch
 };
+
+// Workgroups are dealt to the 8 XCDs round-robin by block index.  Remap so
+// that each XCD runs whole chunks of `chunk` consecutive logical blocks
+// (chunks interleaved over the XCDs, which keeps them balanced): the slices of
+// one tile and neighbouring tiles of one bra pair then share an L2.  The grid
+// is padded to a multiple of 8 chunk; padding blocks return -1.
+__device__ __forceinline__ int xcd_block(int nblk, int chunk) {
+    const int b = (int)blockIdx.x;
+    const int span = 8 * chunk;
+    const int o = b % span;
+    const int lb = (b - o) + (o & 7) * chunk + (o >> 3);
+    return lb < nblk ? lb : -1;
+}
 
 // First slot q in [l, h) with !(Qp Q[q] >= t); Q is sorted descending.
 __device__ __forceinline__ int first_below(const double *Q, int l, int h, double Qp, double t) {
@@ -373,7 +388,7 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
                 if (!__any(kb * b.B >= eps)) break;
                 nprim += act;
                 prim_quartet_p<C, W>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, a.op, a.om2,
-                                     a.boys, acc);
+                                     a.boys, acc, a.om);
             }
         }
         if (act) {
@@ -404,17 +419,23 @@ __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p
 // recomputed per slice instead of exchanged.
 template <class C>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri(QuartetArgs a) {
-    const int w = blockIdx.x % C::NSPLIT;
-    const int t = blockIdx.x / C::NSPLIT;
+    const int lb = xcd_block(a.nblk, 8 * C::NSPLIT);
+    if (lb < 0) return;
+    const int w = lb % C::NSPLIT;
+    int t = lb / C::NSPLIT;
+    const int sub = t % a.nsub;
+    t /= a.nsub;
     const int j = t / a.n_kgrp;
     const int g = t - j * a.n_kgrp;
     const int p = a.bra_first + j * a.bra_stride;
     if (p >= a.n_bra) return;
     int lo = 0;
     const int cut = ket_cut(a, p, g, &lo);
-    if (cut <= lo) return;
-    if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut - lo));
-    tile_dispatch<C, 0>(a, w, p, g, lo, cut);
+    const int lo2 = lo + sub * a.tq;
+    const int cut2 = min(cut, lo2 + a.tq);
+    if (cut2 <= lo2) return;
+    if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut2 - lo2));
+    tile_dispatch<C, 0>(a, w, p, g, lo2, cut2);
 }
 
 // FP32 counterpart of tile_part: FP32 records, recurrences and contraction,
@@ -471,17 +492,23 @@ __device__ __forceinline__ void tile_dispatch32(const QuartetArgs &a, int w, int
 
 template <class C>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri32(QuartetArgs a) {
-    const int w = blockIdx.x % C::NSPLIT;
-    const int t = blockIdx.x / C::NSPLIT;
+    const int lb = xcd_block(a.nblk, 8 * C::NSPLIT);
+    if (lb < 0) return;
+    const int w = lb % C::NSPLIT;
+    int t = lb / C::NSPLIT;
+    const int sub = t % a.nsub;
+    t /= a.nsub;
     const int j = t / a.n_kgrp;
     const int g = t - j * a.n_kgrp;
     const int p = a.bra_first + j * a.bra_stride;
     if (p >= a.n_bra) return;
     int lo = 0;
     const int cut = ket_cut(a, p, g, &lo);
-    if (cut <= lo) return;
-    if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut - lo));
-    tile_dispatch32<C, 0>(a, w, p, g, lo, cut);
+    const int lo2 = lo + sub * a.tq;
+    const int cut2 = min(cut, lo2 + a.tq);
+    if (cut2 <= lo2) return;
+    if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut2 - lo2));
+    tile_dispatch32<C, 0>(a, w, p, g, lo2, cut2);
 }
 
 // ----------------------------------------------------------------------
@@ -556,6 +583,7 @@ __global__ __launch_bounds__(64) void k_schwarz(const PairHdr *__restrict__ hdr,
     const int t = blockIdx.x * 64 + threadIdx.x;
     if (t >= n) return;
     const PairHdr h = hdr[ids[t]];
+    const double om = sqrt(om2);
     double acc[C::NACC];
 #pragma unroll
     for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
@@ -563,7 +591,7 @@ __global__ __launch_bounds__(64) void k_schwarz(const PairHdr *__restrict__ hdr,
         const PrimRec k = prim[h.off + kp];
         for (int bp = 0; bp < h.n; ++bp) {
             const PrimRec b = prim[h.off + bp];
-            prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc);
+            prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc, om);
         }
     }
     double out[C::NOUT];
@@ -587,13 +615,14 @@ __global__ __launch_bounds__(64) void k_primbound(const PairHdr *__restrict__ hd
     const int t = blockIdx.x * 64 + threadIdx.x;
     if (t >= n) return;
     const PairHdr h = hdr[ids[t]];
+    const double om = sqrt(om2);
     constexpr int NA = 2 * C::LA + 1, NB = 2 * C::LB + 1;
     for (int r = 0; r < h.n; ++r) {
         const PrimRec x = prim[h.off + r];
         double acc[C::NACC];
 #pragma unroll
         for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
-        prim_quartet<C>(x, x.z, x.i2z, x.Px, x.Py, x.Pz, x.PAx, x.PAy, x.PAz, x.K, op, om2, tab, acc);
+        prim_quartet<C>(x, x.z, x.i2z, x.Px, x.Py, x.Pz, x.PAx, x.PAy, x.PAz, x.K, op, om2, tab, acc, om);
         double out[C::NOUT];
         C::post(acc, h.ABx, h.ABy, h.ABz, h.ABx, h.ABy, h.ABz, out);
         double mx = 0.0;
@@ -623,6 +652,7 @@ __global__ __launch_bounds__(64) void k_eval(const PairHdr *__restrict__ hdr,
     const int t = blockIdx.x * 64 + threadIdx.x;
     if (t >= n) return;
     const PairHdr bh = hdr[bk[2 * t]], kh = hdr[bk[2 * t + 1]];
+    const double om = sqrt(om2);
     double acc[C::NACC];
 #pragma unroll
     for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
@@ -630,7 +660,7 @@ __global__ __launch_bounds__(64) void k_eval(const PairHdr *__restrict__ hdr,
         const PrimRec k = prim[kh.off + kp];
         for (int bp = 0; bp < bh.n; ++bp) {
             const PrimRec b = prim[bh.off + bp];
-            prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc);
+            prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc, om);
         }
     }
     double v[C::NOUT];

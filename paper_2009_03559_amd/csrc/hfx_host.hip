@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -314,6 +315,19 @@ hfx_status check_opts(const hfx_opts *o) {
 }
 
 int kernel_op(const hfx_opts *o) { return (o->op == HFX_OP_ERFC && o->omega > 0.0) ? 1 : 0; }
+
+// Ket quartets per block of the direct (non-persistent) launches, by total L:
+// cheap classes take longer ranges.  HFX_TQ overrides it (tuning).
+int quartet_block(int L) {
+    static int env = -1;
+    if (env < 0) {
+        const char *e = std::getenv("HFX_TQ");
+        env = (e && *e) ? std::max(64, std::atoi(e)) : 0;
+    }
+    if (env > 0) return env;
+    (void)L;
+    return 64;  // measured best for every class on the 256-atom shard
+}
 
 }  // namespace hfx
 
@@ -654,8 +668,16 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             a.P = P;
             a.K = K;
             a.ld = ld;
-            const int64_t nblk = (int64_t)((B.n - shard + nshards - 1) / nshards) * Kl.ngrp;
-            if (nblk * 16 > INT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
+            // ket ranges are cut into sub-ranges of tq quartets so that no block
+            // runs much longer than the others (quartet-block size per class)
+            const int L = PAIR_L[cb][0] + PAIR_L[cb][1] + PAIR_L[ck][0] + PAIR_L[ck][1];
+            int gmax = 1;
+            for (size_t gi = 0; gi + 1 < Kl.goff.size(); ++gi) gmax = std::max(gmax, Kl.goff[gi + 1] - Kl.goff[gi]);
+            a.tq = quartet_block(L);
+            a.nsub = (gmax + a.tq - 1) / a.tq;
+            const int64_t nblk = (int64_t)((B.n - shard + nshards - 1) / nshards) * Kl.ngrp * a.nsub;
+            if (nblk * 32 > INT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
+            a.om = op ? o->omega : 0.0;
             // FP64: Q_p Q_q >= max(tau, cut) in mixed mode, >= tau otherwise
             a.tau = mixed ? std::max(o->tau, o->mixed_cut) : o->tau;
             a.tau_hi = inf;

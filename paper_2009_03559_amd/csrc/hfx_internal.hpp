@@ -21,6 +21,7 @@ struct ClassList {
 
 hfx_status fail(hfx_status s, const std::string &msg);
 int kernel_op(const hfx_opts *o);
+int quartet_block(int L);
 extern const int PAIR_L[6][2];
 hfx_status check_opts(const hfx_opts *o);
 hfx_status check_P(const double *P, int64_t n, int64_t ld, hipStream_t st);

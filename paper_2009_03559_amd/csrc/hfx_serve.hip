@@ -171,6 +171,8 @@ static void make_jobs(ClassJobs &cj, int ci, int nsys, hfx_pairs const *p, const
         a.n_bra = B.n;
         a.bra_first = 0;
         a.bra_stride = 1;
+        a.nsub = 1;
+        a.tq = 1 << 30;
         a.ket_ids = Kl.d_ids;
         a.ket_Q = Kl.d_Q;
         a.ket_goff = Kl.d_goff;
@@ -179,6 +181,7 @@ static void make_jobs(ClassJobs &cj, int ci, int nsys, hfx_pairs const *p, const
         a.same = (cb == ck);
         a.op = op;
         a.om2 = op ? o->omega * o->omega : 0.0;
+        a.om = op ? o->omega : 0.0;
         a.prim_tau = o->prim_tau;
         a.boys = p[s]->d_boys;
         a.boys32 = p[s]->d_boys32;
