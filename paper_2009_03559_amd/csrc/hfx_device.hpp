@@ -40,6 +40,23 @@ struct PrimRec32 {
     float z, i2z, Px, Py, Pz, PAx, PAy, PAz, K, B;
 };
 
+// Read-only views in the constant address space (scalar loads when uniform).
+typedef __attribute__((address_space(4))) const PrimRec CPrimRec;
+typedef __attribute__((address_space(4))) const PrimRec32 CPrimRec32;
+
+__device__ __forceinline__ PrimRec load_rec(CPrimRec *r) {
+    PrimRec x;
+    x.z = r->z; x.i2z = r->i2z; x.Px = r->Px; x.Py = r->Py; x.Pz = r->Pz;
+    x.PAx = r->PAx; x.PAy = r->PAy; x.PAz = r->PAz; x.K = r->K; x.B = r->B;
+    return x;
+}
+__device__ __forceinline__ PrimRec32 load_rec(CPrimRec32 *r) {
+    PrimRec32 x;
+    x.z = r->z; x.i2z = r->i2z; x.Px = r->Px; x.Py = r->Py; x.Pz = r->Pz;
+    x.PAx = r->PAx; x.PAy = r->PAy; x.PAz = r->PAz; x.K = r->K; x.B = r->B;
+    return x;
+}
+
 constexpr int BOYS_NROW = 577;          // grid points 0 .. 36 step 1/16
 constexpr double BOYS_H = 1.0 / 16.0;
 constexpr double BOYS_INVH = 16.0;
@@ -367,7 +384,14 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
     const int nkp = a.ket_gnp[g];
     const int lane = threadIdx.x;
     const double eps = a.prim_tau;
-    const double bmax = a.prim[bh.off].B;
+    // the bra pair is the same for the whole wave: make that explicit so its
+    // records are read with scalar loads
+    const int boff = __builtin_amdgcn_readfirstlane(bh.off);
+    const int bn = __builtin_amdgcn_readfirstlane(bh.n);
+    // records are read-only during the kernel: the constant address space lets
+    // the uniform loads go through the scalar cache
+    const CPrimRec *brec = (const CPrimRec *)(a.prim + boff);
+    const double bmax = brec->B;
     constexpr int NA = C::NACCP[W];
     unsigned long long nprim = 0;
     for (int q0 = lo; q0 < cut; q0 += 64) {
@@ -383,8 +407,8 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
             const double kb = act ? k.B : 0.0;
             // records are sorted by B: once no lane can reach eps, none will
             if (!__any(kb * bmax >= eps)) break;
-            for (int bp = 0; bp < bh.n; ++bp) {
-                const PrimRec b = a.prim[bh.off + bp];
+            for (int bp = 0; bp < bn; ++bp) {
+                const PrimRec b = load_rec(brec + bp);
                 if (!__any(kb * b.B >= eps)) break;
                 nprim += act;
                 prim_quartet_p<C, W>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, a.op, a.om2,
@@ -446,7 +470,10 @@ __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, 
     const int nkp = a.ket_gnp[g];
     const int lane = threadIdx.x;
     const float eps = (float)a.prim_tau;
-    const float bmax = a.prim32[bh.off].B;
+    const int boff = __builtin_amdgcn_readfirstlane(bh.off);
+    const int bn = __builtin_amdgcn_readfirstlane(bh.n);
+    const CPrimRec32 *brec = (const CPrimRec32 *)(a.prim32 + boff);
+    const float bmax = brec->B;
     const float om2 = (float)a.om2, om = sqrtf(om2);
     constexpr int NA = C::NACCP[W];
     unsigned long long nprim = 0;
@@ -462,8 +489,8 @@ __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, 
             const PrimRec32 k = a.prim32[kh.off + kp];
             const float kb = act ? k.B : 0.0f;
             if (!__any(kb * bmax >= eps)) break;
-            for (int bp = 0; bp < bh.n; ++bp) {
-                const PrimRec32 b = a.prim32[bh.off + bp];
+            for (int bp = 0; bp < bn; ++bp) {
+                const PrimRec32 b = load_rec(brec + bp);
                 if (!__any(kb * b.B >= eps)) break;
                 nprim += act;
                 prim_quartet32<C, W>(b, k, a.op, om, om2, a.boys32, acc);
