@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle timing leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
-    ap.add_argument("--mixed-cut", type=float, default=1e-6, help="tuned FP32 cut on Q_IJ Q_KL")
+    ap.add_argument("--mixed-cut", type=float, default=1e-7, help="tuned FP32 cut on Q_IJ Q_KL")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
     ap.add_argument("--batch-natom", type=str, default="6,20",
@@ -78,15 +78,16 @@ def cpu_baseline(sysm, tau, omega, budget_s):
     keep = qpool[ii] * qpool[jj] >= tau
     cand = np.stack([pool[ii[keep]], pool[jj[keep]]], axis=1)
     rng.shuffle(cand)
-    probe = cand[:256]
-    t0 = time.perf_counter()
-    oracle.digest_list(sysm, probe, omega=omega, nthreads=cores)
-    dt = time.perf_counter() - t0
-    n = int(max(256, min(len(cand), 256 * budget_s / max(dt, 1e-3))))
-    sample = cand[:n]
-    t0 = time.perf_counter()
-    oracle.digest_list(sysm, sample, omega=omega, nthreads=cores)
-    dt = time.perf_counter() - t0
+    # grow the sample until it takes about a third of the budget, then time it
+    n = 512
+    while True:
+        sample = cand[:n]
+        t0 = time.perf_counter()
+        oracle.digest_list(sysm, sample, omega=omega, nthreads=cores)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 3 or n >= len(cand):
+            break
+        n = min(len(cand), int(n * max(2.0, budget_s / 2 / max(dt, 1e-3))))
     desc = (f"{n} screened unique shell quartets (Q_IJ Q_KL >= tau by the oracle's own Schwarz factors) "
             f"among a seeded random pool of {len(pool)} shell pairs of the same system; FP64 integrals and "
             f"digestion into K; {dt:.1f} s")
