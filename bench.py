@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--serve-natom", type=str, default="6,24",
                     help="atom-count range of served requests (scaled-down config-4 recipe)")
     ap.add_argument("--serve-requests", type=int, default=12)
+    ap.add_argument("--config2", action="store_true",
+                    help="only the 1024-atom mixed-precision workload: full K of the 128-atom subset in FP64 and "
+                         "mixed, and one shard of the 1024-atom build")
+    ap.add_argument("--config2-shards", type=int, default=2048)
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 512 MiB device copy five times (HBM counter calibration)")
     return ap.parse_args()
@@ -243,10 +247,95 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8, "launches": 5}))
 
 
+def screened_count(s, Q, tau):
+    """Screened unique quartets of system s, counted with numpy from the
+    Schwarz factors alone (a check on the kernels' own count)."""
+    n = s.nshell
+    I = np.repeat(np.arange(n), np.arange(1, n + 1))
+    J = np.concatenate([np.arange(i + 1) for i in range(n)])
+    la = np.maximum(s.shell_l[I], s.shell_l[J])
+    lb = np.minimum(s.shell_l[I], s.shell_l[J])
+    cls = la * (la + 1) // 2 + lb
+    total = 0
+    for cb in range(6):
+        qb = Q[cls == cb]
+        qb = qb[qb > 0]
+        for ck in range(cb + 1):
+            qk = np.sort(Q[cls == ck])
+            cnt = int((len(qk) - np.searchsorted(qk, tau / qb, side="left")).sum())
+            if cb == ck:
+                cnt = (cnt + int((qb * qb >= tau).sum())) // 2
+            total += cnt
+    return total
+
+
+def config2_leg(a):
+    """Mixed precision on the config-1 recipe at 1024 atoms (13312 functions).
+    The 128 atoms nearest the centroid: full K in FP64 (the parity-checked
+    path) and in mixed precision, max-abs and tr(PK) differences, speedup.
+    The 1024-atom system: one bra-pair shard in FP64 and mixed."""
+    import torch
+
+    import hfx_inputs as hi
+    import paper_2009_03559_amd as hfx
+
+    torch.cuda.init()
+    tau, omega = 1e-10, hi.OMEGA_HSE
+    big = hi.config2()
+    sub = hi.config2_subset(big, 128)
+    out = {"metric": "config-2 mixed precision", "workload": f"config-1 recipe at 1024 atoms ({big.nbf} functions); "
+           f"128-atom subset nearest the centroid ({sub.nbf} functions)", "mixed_cut": a.mixed_cut}
+    res = {}
+    pairs = hfx.pairs_from_system(sub)
+    P = torch.from_numpy(sub.P).cuda()
+    want = screened_count(sub, hfx.schwarz_bounds(pairs, hfx.opts(tau=tau, omega=omega)), tau)
+    for name, prec in (("fp64", hfx.PREC_FP64), ("mixed", hfx.PREC_MIXED)):
+        o = hfx.opts(tau=tau, omega=omega, prec=prec, mixed_cut=a.mixed_cut)
+        K = torch.empty_like(P)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = hfx.build_K(pairs, P, K, o, stats=True)
+        torch.cuda.synchronize()
+        res[name] = (K.cpu().numpy(), time.perf_counter() - t0, st)
+        print(f"# subset {name}: {res[name][1]:.2f} s, {st['quartets']} quartets ({want} screened)",
+              file=sys.stderr, flush=True)
+        if st["quartets"] != want:
+            raise SystemExit(f"subset {name}: evaluated {st['quartets']} quartets, screening keeps {want}")
+    K64, t64, s64 = res["fp64"]
+    Km, tm, sm = res["mixed"]
+    out["subset128"] = {"quartets": s64["quartets"], "quartets_screened_numpy": want, "fp64_s": t64, "mixed_s": tm, "speedup": t64 / tm,
+                        "fp32_quartet_fraction": sm["quartets_fp32"] / max(1, sm["quartets"]),
+                        "max_abs_dK_mixed_vs_fp64_gpu": float(np.abs(Km - K64).max()),
+                        "trPK_err_mixed_vs_fp64_gpu": float(abs(np.sum(sub.P * Km) - np.sum(sub.P * K64))),
+                        "fp64_quartets_per_s": s64["quartets"] / t64, "mixed_quartets_per_s": sm["quartets"] / tm}
+    del pairs, P
+    pb = hfx.pairs_from_system(big)
+    Pb = torch.from_numpy(big.P).cuda()
+    Kb = torch.empty_like(Pb)
+    shard = {}
+    hfx.schwarz_bounds(pb, hfx.opts(tau=tau, omega=omega))
+    for name, prec in (("fp64", hfx.PREC_FP64), ("mixed", hfx.PREC_MIXED)):
+        o = hfx.opts(tau=tau, omega=omega, prec=prec, mixed_cut=a.mixed_cut)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = hfx.build_K_shard(pb, Pb, Kb, o, 0, a.config2_shards, stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        shard[name] = {"s": dt, "quartets": st["quartets"], "quartets_per_s": st["quartets"] / dt,
+                       "projected_full_build_s": st["device_s"] * a.config2_shards}
+        print(f"# 1024-atom shard {name}: {dt:.2f} s", file=sys.stderr, flush=True)
+    shard["speedup"] = shard["fp64"]["s"] / shard["mixed"]["s"]
+    out["shard_of_1024"] = dict(shard, shards=a.config2_shards)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_calib:
         copy_calibration()
+        return
+    if a.config2:
+        config2_leg(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported in this build "

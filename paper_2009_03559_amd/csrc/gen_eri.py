@@ -573,11 +573,10 @@ def generate(outdir, T="double", splits=None):
                 f'#include "eri_{tag}{suffix}.h"',
                 "namespace hfx {",
                 f"void launch_eri32_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
-                "  QuartetArgs a = a0;",
-                f"  a.nblk = (int)(nblk * {nm}::NSPLIT);",
-                f"  const unsigned span = 64u * {nm}::NSPLIT;  // 8 XCDs x chunk",
-                "  const unsigned grid = ((unsigned)a.nblk + span - 1) / span * span;",
-                f"  hipLaunchKernelGGL(k_eri32<{nm}>, dim3(grid), dim3(64), 0, s, a);",
+                f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,  // 8 XCDs x chunk",
+                "                  [&](const QuartetArgs &a, unsigned grid) {",
+                f"                    hipLaunchKernelGGL(k_eri32<{nm}>, dim3(grid), dim3(64), 0, s, a);",
+                "                  });",
                 "}",
                 f"void launch_persist32_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
                 "                          unsigned grid, hipStream_t s) {",
@@ -595,11 +594,10 @@ def generate(outdir, T="double", splits=None):
             f'#include "eri_{tag}{suffix}.h"',
             "namespace hfx {",
             f"void launch_eri_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
-            "  QuartetArgs a = a0;",
-            f"  a.nblk = (int)(nblk * {nm}::NSPLIT);",
-            f"  const unsigned span = 64u * {nm}::NSPLIT;  // 8 XCDs x chunk",
-            "  const unsigned grid = ((unsigned)a.nblk + span - 1) / span * span;",
-            f"  hipLaunchKernelGGL(k_eri<{nm}>, dim3(grid), dim3(64), 0, s, a);",
+            f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,  // 8 XCDs x chunk",
+            "                  [&](const QuartetArgs &a, unsigned grid) {",
+            f"                    hipLaunchKernelGGL(k_eri<{nm}>, dim3(grid), dim3(64), 0, s, a);",
+            "                  });",
             "}",
             f"void launch_persist_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
             "                        unsigned grid, hipStream_t s) {",

@@ -313,7 +313,8 @@ struct QuartetArgs {
     int32_t bra_stride;
     int32_t nsub;             // ket sub-ranges per (bra slot, ket group) block row
     int32_t tq;               // ket quartets per sub-range
-    int32_t nblk;             // logical blocks (the grid is padded to a multiple of 8)
+    int32_t nblk;             // logical blocks of this launch (grid padded to whole XCD spans)
+    long long blk_base;       // first logical block of this launch (long grids run in segments)
     double om;                // omega
     const int32_t *ket_ids;   // ket class, same order
     const double *ket_Q;
@@ -346,6 +347,23 @@ __device__ __forceinline__ int xcd_block(int nblk, int chunk) {
     const int o = b % span;
     const int lb = (b - o) + (o & 7) * chunk + (o >> 3);
     return lb < nblk ? lb : -1;
+}
+
+// The dispatch packet holds the grid size as a 32-bit count of work-items, so
+// a launch must stay well below 2^32 / 64 blocks.  A longer grid is launched in
+// segments of whole XCD spans; each segment carries its first logical block.
+long long max_blocks_per_launch();
+
+template <class Launch>
+inline void launch_segments(QuartetArgs a, long long total, long long span, Launch launch) {
+    const long long cap = max_blocks_per_launch() / span * span;
+    const long long seg = cap > span ? cap : span;
+    for (long long base = 0; base < total; base += seg) {
+        const long long n = total - base < seg ? total - base : seg;
+        a.blk_base = base;
+        a.nblk = (int32_t)n;
+        launch(a, (unsigned)((n + span - 1) / span * span));
+    }
 }
 
 // First slot q in [l, h) with !(Qp Q[q] >= t); Q is sorted descending.
@@ -443,14 +461,15 @@ __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p
 // recomputed per slice instead of exchanged.
 template <class C>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri(QuartetArgs a) {
-    const int lb = xcd_block(a.nblk, 8 * C::NSPLIT);
-    if (lb < 0) return;
-    const int w = lb % C::NSPLIT;
-    int t = lb / C::NSPLIT;
-    const int sub = t % a.nsub;
+    const int lb0 = xcd_block(a.nblk, 8 * C::NSPLIT);
+    if (lb0 < 0) return;
+    const long long lb = a.blk_base + lb0;
+    const int w = (int)(lb % C::NSPLIT);
+    long long t = lb / C::NSPLIT;
+    const int sub = (int)(t % a.nsub);
     t /= a.nsub;
-    const int j = t / a.n_kgrp;
-    const int g = t - j * a.n_kgrp;
+    const int j = (int)(t / a.n_kgrp);
+    const int g = (int)(t - (long long)j * a.n_kgrp);
     const int p = a.bra_first + j * a.bra_stride;
     if (p >= a.n_bra) return;
     int lo = 0;
@@ -519,14 +538,15 @@ __device__ __forceinline__ void tile_dispatch32(const QuartetArgs &a, int w, int
 
 template <class C>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri32(QuartetArgs a) {
-    const int lb = xcd_block(a.nblk, 8 * C::NSPLIT);
-    if (lb < 0) return;
-    const int w = lb % C::NSPLIT;
-    int t = lb / C::NSPLIT;
-    const int sub = t % a.nsub;
+    const int lb0 = xcd_block(a.nblk, 8 * C::NSPLIT);
+    if (lb0 < 0) return;
+    const long long lb = a.blk_base + lb0;
+    const int w = (int)(lb % C::NSPLIT);
+    long long t = lb / C::NSPLIT;
+    const int sub = (int)(t % a.nsub);
     t /= a.nsub;
-    const int j = t / a.n_kgrp;
-    const int g = t - j * a.n_kgrp;
+    const int j = (int)(t / a.n_kgrp);
+    const int g = (int)(t - (long long)j * a.n_kgrp);
     const int p = a.bra_first + j * a.bra_stride;
     if (p >= a.n_bra) return;
     int lo = 0;

@@ -329,6 +329,14 @@ int quartet_block(int L) {
     return 64;  // measured best for every class on the 256-atom shard
 }
 
+// Blocks per direct launch: 2^24 blocks of 64 lanes is 2^30 work-items, a
+// quarter of the dispatch packet's 32-bit limit.  HFX_MAX_BLOCKS lowers it
+// (the tests use that to run the segmented path on small systems).
+long long max_blocks_per_launch() {
+    const char *e = std::getenv("HFX_MAX_BLOCKS");
+    return (e && *e) ? std::min(1ll << 24, std::max(1ll, std::atoll(e))) : (1ll << 24);
+}
+
 }  // namespace hfx
 
 using namespace hfx;
@@ -676,7 +684,7 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             a.tq = quartet_block(L);
             a.nsub = (gmax + a.tq - 1) / a.tq;
             const int64_t nblk = (int64_t)((B.n - shard + nshards - 1) / nshards) * Kl.ngrp * a.nsub;
-            if (nblk * 32 > INT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
+            if (nblk > (int64_t)UINT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
             a.om = op ? o->omega : 0.0;
             // FP64: Q_p Q_q >= max(tau, cut) in mixed mode, >= tau otherwise
             a.tau = mixed ? std::max(o->tau, o->mixed_cut) : o->tau;

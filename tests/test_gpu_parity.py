@@ -199,6 +199,53 @@ def test_repeat_build_reuses_lists_and_is_stable():
     assert torch.allclose(K2, 2.0 * K1, rtol=1e-12, atol=1e-14)
 
 
+def _class_counts(s, Q, tau):
+    """Screened unique quartets per (bra class, ket class), counted with numpy
+    from the Schwarz factors alone: pair classes by (max l, min l), bra class >=
+    ket class, and within one class only the lower triangle of pair pairs."""
+    n = s.nshell
+    I = np.repeat(np.arange(n), np.arange(1, n + 1))
+    J = np.concatenate([np.arange(i + 1) for i in range(n)])
+    la = np.maximum(s.shell_l[I], s.shell_l[J])
+    lb = np.minimum(s.shell_l[I], s.shell_l[J])
+    cls = la * (la + 1) // 2 + lb
+    out = np.zeros(21, dtype=np.int64)
+    for cb in range(6):
+        for ck in range(cb + 1):
+            qb, qk = Q[cls == cb], np.sort(Q[cls == ck])
+            cnt = sum(len(qk) - np.searchsorted(qk, tau / q, side="left") for q in qb if q > 0)
+            if cb == ck:
+                cnt = (cnt + int((qb * qb >= tau).sum())) // 2
+            out[cb * (cb + 1) // 2 + ck] = cnt
+    return out
+
+
+@pytest.mark.parametrize("prec", [hfx.PREC_FP64, hfx.PREC_MIXED])
+def test_segmented_launch(monkeypatch, prec):
+    """A class grid above the per-launch block limit runs as several launches,
+    each starting at its own logical block.  Forcing a limit of one XCD span
+    cuts every class of a 12-atom lattice into many segments: every screened
+    quartet is still evaluated once (per-class counts equal an independent
+    count) and K equals the single-launch K."""
+    s = hi.lattice_system(12, seed=31, nprim_range=(1, 3))
+    o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE, prec=prec)
+    p = hfx.pairs_from_system(s, o)
+    P = torch.from_numpy(s.P).cuda()
+    K1, K2 = torch.empty_like(P), torch.empty_like(P)
+    st1 = hfx.build_K(p, P, K1, o, stats=True)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("HFX_MAX_BLOCKS", "1")
+    _say("segmented launch, 12 atoms, prec", prec)
+    st2 = hfx.build_K(p, P, K2, o, stats=True)
+    torch.cuda.synchronize()
+    monkeypatch.delenv("HFX_MAX_BLOCKS")
+    want = _class_counts(s, hfx.schwarz_bounds(p, o), 1e-10)
+    assert list(st1["class_quartets"]) == list(want)
+    assert list(st2["class_quartets"]) == list(want)
+    assert st2["quartets_fp32"] == st1["quartets_fp32"]
+    assert torch.abs(K2 - K1).max().item() <= 1e-12
+
+
 def test_full_size_config1_sampled():
     """configs-1 system at full size (1280 shells): all 819,840 Schwarz factors
     on the GPU; a sample of them and of raw quartet integrals (every class)
