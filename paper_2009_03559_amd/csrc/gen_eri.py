@@ -97,8 +97,15 @@ class Emitter:
 
 
 # ------------------------------------------------------------------ VRR ----
-def vrr_graph(la, lb, lc, ld, f_targets=None, policy="auto"):
-    """Needed nodes (e, f, m) and each node's recurrence (direction, preds)."""
+def vrr_graph(la, lb, lc, ld, f_targets=None, policy="auto", last="auto"):
+    """Needed nodes (e, f, m) and each node's recurrence (direction, preds).
+
+    `last` picks the side whose steps are applied last when both e and f are
+    non-zero: "ket" builds [e0|00] first and raises f on top of it (with the
+    coupling term to e - 1_i); "bra" builds [00|f0] first and raises e on top
+    (coupling to f - 1_i).  For a slice that holds only some f components the
+    "bra" order needs only the ket base of those components, while "ket"
+    rebuilds the whole bra table in every slice."""
     E, F = la + lb, lc + ld
     L = E + F
     e_t = [e for d in range(la, E + 1) for e in cart(d)]
@@ -106,7 +113,8 @@ def vrr_graph(la, lb, lc, ld, f_targets=None, policy="auto"):
     f_t = f_all if f_targets is None else f_targets
     best = None
     policies = ["first", "small", "large", "last"] if policy == "auto" else [policy]
-    for pol in policies:
+    lasts = ["ket", "bra"] if last == "auto" else [last]
+    for pol, side in ((p_, s_) for s_ in lasts for p_ in policies):
         rec = {}
 
         def pick(t):
@@ -131,7 +139,7 @@ def vrr_graph(la, lb, lc, ld, f_targets=None, policy="auto"):
                 rec[node] = ("base",)
                 order.append(node)
                 return
-            if sum(f) > 0:
+            if sum(f) > 0 and (side == "ket" or sum(e) == 0):
                 i = pick(f)
                 f1 = sub(f, i)
                 preds = [("QC", i, (e, f1, m)), ("WQ", i, (e, f1, m + 1))]
@@ -148,6 +156,8 @@ def vrr_graph(la, lb, lc, ld, f_targets=None, policy="auto"):
                 if e1[i] > 0:
                     e2 = sub(e1, i)
                     preds.append(("E2", i, e1[i], (e2, f, m), (e2, f, m + 1)))
+                if f[i] > 0:
+                    preds.append(("FX", i, f[i], (e1, sub(f, i), m + 1)))
                 kind = "bra"
             for p in preds:
                 for x in p:
@@ -162,7 +172,7 @@ def vrr_graph(la, lb, lc, ld, f_targets=None, policy="auto"):
                 need((e, f, 0))
         cost = sum(_node_flops(rec[n]) for n in order)
         if best is None or cost < best[0]:
-            best = (cost, rec, order, pol)
+            best = (cost, rec, order, (pol, side))
     return best[1], best[2], e_t, f_t, best[0]
 
 
@@ -175,7 +185,7 @@ def _node_flops(r):
             n += 2
         elif p[0] in ("F2", "E2"):
             n += 4
-        elif p[0] == "EX":
+        elif p[0] in ("EX", "FX"):
             n += 2
     return n
 
@@ -218,7 +228,7 @@ def emit_vrr(em, la, lb, lc, ld, name, f_targets=None, policy="auto"):
                 c = p[2]
                 coef = "i2z" if c == 1 else f"({em.lit(c)} * i2z)"
                 terms.append(f"{coef} * (v{ids[p[3]]} - roz * v{ids[p[4]]})")
-            elif tag == "EX":
+            elif tag in ("EX", "FX"):
                 c = p[2]
                 coef = "i2ze" if c == 1 else f"({em.lit(c)} * i2ze)"
                 terms.append(f"{coef} * v{ids[p[3]]}")
@@ -482,11 +492,11 @@ PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 
 # Number of ket slices (waves) per quartet for the classes whose contracted
 # array does not fit one lane's registers.  Measured on the 256-atom DZP
-# shard: more slices than these slow the mid classes (recomputed shared
-# recurrence), fewer spill registers in the high classes.
+# shard: fewer slices than these spill registers to scratch (2-3x slower),
+# more slices recompute more of the shared recurrence.
 DEFAULT_SPLITS = {
-    (2, 1, 1, 1): 2, (2, 1, 2, 0): 2, (2, 2, 1, 0): 2, (2, 2, 2, 0): 4,
-    (2, 1, 2, 1): 4, (2, 2, 1, 1): 4, (2, 2, 2, 1): 16, (2, 2, 2, 2): 31,
+    (2, 1, 1, 1): 2, (2, 1, 2, 0): 1, (2, 2, 1, 0): 1, (2, 2, 2, 0): 2,
+    (2, 1, 2, 1): 3, (2, 2, 1, 1): 3, (2, 2, 2, 1): 6, (2, 2, 2, 2): 12,
 }
 
 # Override for tuning: HFX_SPLITS="2221:16,2222:32".
@@ -494,12 +504,22 @@ for _kv in filter(None, os.environ.get("HFX_SPLITS", "").split(",")):
     _k, _v = _kv.split(":")
     DEFAULT_SPLITS[tuple(int(c) for c in _k)] = int(_v)
 
-# FP32 slices: the same as FP64 (fewer slices spill in FP32 too).
-DEFAULT_SPLITS_F32 = dict(DEFAULT_SPLITS)
+# FP32 slices: an FP32 value takes half the registers, so fewer slices fit
+# (measured the same way).
+DEFAULT_SPLITS_F32 = {
+    (2, 1, 1, 1): 1, (2, 1, 2, 0): 1, (2, 2, 1, 0): 1, (2, 2, 2, 0): 1,
+    (2, 1, 2, 1): 2, (2, 2, 1, 1): 2, (2, 2, 2, 1): 3, (2, 2, 2, 2): 6,
+}
+for _kv in filter(None, os.environ.get("HFX_SPLITS_F32", "").split(",")):
+    _k, _v = _kv.split(":")
+    DEFAULT_SPLITS_F32[tuple(int(c) for c in _k)] = int(_v)
 
 # Minimum waves per SIMD asked of the register allocator, per class (classes
-# not listed: 1).
-WAVES = {}
+# not listed: 1).  (ds|ds) gains from two waves; the other mid classes lose.
+WAVES = {(2, 0, 2, 0): 2}
+for _kv in filter(None, os.environ.get("HFX_WAVES", "").split(",")):
+    _k, _v = _kv.split(":")
+    WAVES[tuple(int(c) for c in _k)] = int(_v)
 
 
 def class_tag(c):
