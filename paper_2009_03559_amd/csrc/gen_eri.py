@@ -214,6 +214,8 @@ def emit_vrr(em, la, lb, lc, ld, name, f_targets=None, policy="auto"):
         v = f"v{ids[n]}"
         if r[0] == "base":
             em.lines.append(f"    const {T} {v} = g[{m}];")
+            if m == 0 and (e, f) in acc_index:
+                em.lines.append(f"    acc[{acc_index[(e, f)]}] += {v};")
             continue
         terms = []
         for p in r[1]:
@@ -233,8 +235,9 @@ def emit_vrr(em, la, lb, lc, ld, name, f_targets=None, policy="auto"):
                 coef = "i2ze" if c == 1 else f"({em.lit(c)} * i2ze)"
                 terms.append(f"{coef} * v{ids[p[3]]}")
         em.lines.append(f"    const {T} {v} = " + " + ".join(terms) + ";")
-    for (e, f), a in acc_index.items():
-        em.lines.append(f"    acc[{a}] += v{ids[(e, f, 0)]};")
+        if m == 0 and (e, f) in acc_index:
+            # accumulate a target as soon as it exists: its value dies here
+            em.lines.append(f"    acc[{acc_index[(e, f)]}] += {v};")
     em.lines.append("  }")
     return nacc, cost + nacc  # accumulation adds
 
@@ -495,7 +498,7 @@ PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 # shard: fewer slices than these spill registers to scratch (2-3x slower),
 # more slices recompute more of the shared recurrence.
 DEFAULT_SPLITS = {
-    (2, 1, 1, 1): 2, (2, 1, 2, 0): 1, (2, 2, 1, 0): 1, (2, 2, 2, 0): 2,
+    (2, 1, 1, 1): 2, (2, 1, 2, 0): 1, (2, 2, 1, 0): 1, (2, 2, 2, 0): 3,
     (2, 1, 2, 1): 3, (2, 2, 1, 1): 3, (2, 2, 2, 1): 6, (2, 2, 2, 2): 12,
 }
 
