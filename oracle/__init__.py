@@ -55,6 +55,9 @@ def lib():
         L.oracle_build_K.restype = ctypes.c_int
         L.oracle_build_K.argtypes = basis + [_f64p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                              _f64p, _f64p, _i64p]
+        L.oracle_build_JK.restype = ctypes.c_int
+        L.oracle_build_JK.argtypes = basis + [_f64p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                              _f64p, _f64p, _f64p, _i64p]
         L.oracle_digest_list.restype = ctypes.c_int
         L.oracle_digest_list.argtypes = basis + [_f64p, ctypes.c_double, ctypes.c_int64, _i64p,
                                                  ctypes.c_int, _f64p]
@@ -137,6 +140,24 @@ def build_K(sys, tau=1e-10, omega=0.0, nthreads=0, P=None):
         raise ValueError("oracle_build_K: invalid basis")
     return K, Q[:npair], dict(quartets=int(cnt[0]), prim_quartets=int(cnt[1]),
                                per_class=cnt[2:].copy())
+
+
+def build_JK(sys, tau=1e-10, omega=0.0, nthreads=0, P=None):
+    """Coulomb J_ij = sum_kl (ij|kl) P_kl and exchange K from the same screened
+    unique quartets.  Returns (J, K, Q, counts) as build_K."""
+    n = sys.nbf
+    P = np.ascontiguousarray(sys.P if P is None else P, dtype=np.float64)
+    J = np.zeros((n, n), dtype=np.float64)
+    K = np.zeros((n, n), dtype=np.float64)
+    npair = sys.nshell * (sys.nshell + 1) // 2
+    Q = np.zeros(max(npair, 1), dtype=np.float64)
+    cnt = np.zeros(23, dtype=np.int64)
+    rc = lib().oracle_build_JK(*_basis_args(sys), P.ravel(), float(tau), float(omega), int(nthreads),
+                               J.ravel(), K.ravel(), Q, cnt)
+    if rc:
+        raise ValueError("oracle_build_JK: invalid basis")
+    return J, K, Q[:npair], dict(quartets=int(cnt[0]), prim_quartets=int(cnt[1]),
+                                  per_class=cnt[2:].copy())
 
 
 def digest_list(sys, pairs_pq: np.ndarray, omega=0.0, nthreads=0, P=None) -> np.ndarray:

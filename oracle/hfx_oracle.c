@@ -516,6 +516,29 @@ static void digest(const double *blk, int I, int J, int K, int L, const int *bfo
     }
 }
 
+/* Coulomb digestion of the same unique quartet (the Hartree term):
+ * J_ij = sum_kl (ij|kl) P_kl.  The eight permutations of (ij|kl) update
+ * J_ij, J_ji with v P_kl twice each and J_kl, J_lk with v P_ij twice each
+ * (P symmetric), so with the same degeneracy factor d:
+ *   J'_ij += 2 d v P_kl,  J'_kl += 2 d v P_ij,  then J = J' + J'^T.        */
+static void digest_J(const double *blk, int I, int J, int K, int L, const int *bfo, const int32_t *l,
+                     const double *P, int64_t n, double *Jp) {
+    double d = 2.0;
+    if (I == J) d *= 0.5;
+    if (K == L) d *= 0.5;
+    if (I == K && J == L) d *= 0.5;
+    int ni = nsph(l[I]), nj = nsph(l[J]), nk = nsph(l[K]), nl = nsph(l[L]);
+    for (int i = 0; i < ni; i++)
+    for (int j = 0; j < nj; j++)
+    for (int k = 0; k < nk; k++)
+    for (int q = 0; q < nl; q++) {
+        double v = d * blk[((i * nj + j) * nk + k) * nl + q];
+        int64_t gi = bfo[I] + i, gj = bfo[J] + j, gk = bfo[K] + k, gl = bfo[L] + q;
+        Jp[gi * n + gj] += v * P[gk * n + gl];
+        Jp[gk * n + gl] += v * P[gi * n + gj];
+    }
+}
+
 static int pair_I(int64_t p) {
     int I = (int)((sqrt(8.0 * (double)p + 1) - 1) / 2);
     while ((int64_t)I * (I + 1) / 2 > p) I--;
@@ -539,10 +562,10 @@ int oracle_class_index(int la, int lb, int lc, int ld) {
     return cb * (cb + 1) / 2 + ck;
 }
 
-int oracle_build_K(const double *xyz, int nshell, const int32_t *atom, const int32_t *l,
-                   const int32_t *nprim, const int32_t *off, const double *exps,
-                   const double *coefs, const double *P, double tau, double omega,
-                   int nthreads, double *K, double *Q_out, int64_t *counts) {
+static int build_JK(const double *xyz, int nshell, const int32_t *atom, const int32_t *l,
+                    const int32_t *nprim, const int32_t *off, const double *exps,
+                    const double *coefs, const double *P, double tau, double omega,
+                    int nthreads, double *Jout, double *K, double *Q_out, int64_t *counts) {
     basis_t B; double *cn;
     if (setup_basis(&B, xyz, nshell, atom, l, nprim, off, exps, coefs, &cn)) return 1;
     int *bfo = malloc(sizeof(int) * (nshell + 1));
@@ -558,11 +581,13 @@ int oracle_build_K(const double *xyz, int nshell, const int32_t *atom, const int
     double qmax = 0;
     for (int64_t p = 0; p < npair; p++) if (Q[p] > qmax) qmax = Q[p];
     memset(K, 0, sizeof(double) * n * n);
+    if (Jout) memset(Jout, 0, sizeof(double) * n * n);
     int64_t cnt[2 + 21] = {0};
     #pragma omp parallel
     {
         vtab_t *W = malloc(sizeof(vtab_t));
         double *Kp = calloc((size_t)(n * n), sizeof(double));
+        double *Jp = Jout ? calloc((size_t)(n * n), sizeof(double)) : NULL;
         int64_t lc_[2 + 21] = {0};
         double blk[625];
         #pragma omp for schedule(dynamic, 1)
@@ -575,6 +600,7 @@ int oracle_build_K(const double *xyz, int nshell, const int32_t *atom, const int
                 int Kk = pair_I(q), Ll = (int)(q - (int64_t)Kk * (Kk + 1) / 2);
                 shell_quartet(&B, I, J, Kk, Ll, omega, W, blk);
                 digest(blk, I, J, Kk, Ll, bfo, l, P, n, Kp);
+                if (Jp) digest_J(blk, I, J, Kk, Ll, bfo, l, P, n, Jp);
                 lc_[0]++;
                 lc_[1] += (int64_t)nprim[I] * nprim[J] * nprim[Kk] * nprim[Ll];
                 lc_[2 + oracle_class_index(l[I], l[J], l[Kk], l[Ll])]++;
@@ -583,20 +609,44 @@ int oracle_build_K(const double *xyz, int nshell, const int32_t *atom, const int
         #pragma omp critical
         {
             for (int64_t x = 0; x < n * n; x++) K[x] += Kp[x];
+            if (Jp) for (int64_t x = 0; x < n * n; x++) Jout[x] += Jp[x];
             for (int c = 0; c < 23; c++) cnt[c] += lc_[c];
         }
-        free(Kp); free(W);
+        free(Kp); free(Jp); free(W);
     }
-    /* K = K' + K'^T */
+    /* K = K' + K'^T, J = J' + J'^T */
     for (int64_t i = 0; i < n; i++)
         for (int64_t j = i; j < n; j++) {
             double s = K[i * n + j] + K[j * n + i];
             K[i * n + j] = s; K[j * n + i] = s;
+            if (Jout) {
+                double t = Jout[i * n + j] + Jout[j * n + i];
+                Jout[i * n + j] = t; Jout[j * n + i] = t;
+            }
         }
     if (Q_out) memcpy(Q_out, Q, sizeof(double) * npair);
     if (counts) memcpy(counts, cnt, sizeof(cnt));
     free(Q); free(bfo); free(cn);
     return 0;
+}
+
+int oracle_build_K(const double *xyz, int nshell, const int32_t *atom, const int32_t *l,
+                   const int32_t *nprim, const int32_t *off, const double *exps,
+                   const double *coefs, const double *P, double tau, double omega,
+                   int nthreads, double *K, double *Q_out, int64_t *counts) {
+    return build_JK(xyz, nshell, atom, l, nprim, off, exps, coefs, P, tau, omega, nthreads,
+                    NULL, K, Q_out, counts);
+}
+
+/* Coulomb and exchange from the same screened quartets: J_ij = sum_kl (ij|kl)
+ * P_kl next to K_ik = sum_jl (ij|kl) P_jl (the Hartree and exchange terms of
+ * the total-energy expression, Sec. 2).  Same screening and counts.         */
+int oracle_build_JK(const double *xyz, int nshell, const int32_t *atom, const int32_t *l,
+                    const int32_t *nprim, const int32_t *off, const double *exps,
+                    const double *coefs, const double *P, double tau, double omega,
+                    int nthreads, double *J, double *K, double *Q_out, int64_t *counts) {
+    return build_JK(xyz, nshell, atom, l, nprim, off, exps, coefs, P, tau, omega, nthreads,
+                    J, K, Q_out, counts);
 }
 
 /* Digest an explicit list of unique shell quartets (I,J,K,L given as pair

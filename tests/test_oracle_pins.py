@@ -386,6 +386,51 @@ def test_config0_K_brute_force_both_operators():
         assert np.trace(s.P @ K) > 0
 
 
+# ------------------------------------------------ Coulomb J (next row) ----
+@pytest.mark.parametrize("omega", [0.0, 0.11])
+def test_J_brute_force_and_coulomb_energy(small_spd, omega):
+    """J from the unique quartets equals the n^4 contraction
+    J_ij = sum_kl (ij|kl) P_kl; J is symmetric; the Coulomb energy
+    sum_ijkl P_ij (ij|kl) P_kl is non-negative for any symmetric P (the kernel
+    1/r and erfc(omega r)/r is positive definite); K from the joint build is
+    the exchange of the K-only build."""
+    s = small_spd
+    G = oracle.eri_tensor(s, omega=omega)
+    J, K, Q, cnt = oracle.build_JK(s, tau=0.0, omega=omega)
+    Jb = np.einsum("ijkl,kl->ij", G, s.P)
+    assert np.abs(J - Jb).max() <= 1e-13 * np.abs(Jb).max()
+    assert np.abs(J - J.T).max() == 0.0
+    K1, _, cnt1 = oracle.build_K(s, tau=0.0, omega=omega)
+    assert np.abs(K - K1).max() <= 1e-14 * np.abs(K1).max()
+    assert cnt["quartets"] == cnt1["quartets"] and (cnt["per_class"] == cnt1["per_class"]).all()
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        A = rng.standard_normal((s.nbf, s.nbf))
+        Ps = A + A.T
+        Jr, _, _, _ = oracle.build_JK(s, tau=0.0, omega=omega, P=Ps)
+        assert np.sum(Ps * Jr) >= -1e-12 * np.abs(Jr).max()
+
+
+def test_J_single_s_function_closed_form():
+    """One normalised s function with P = [[p]]: J = K = p (ss|ss), the
+    one-centre value of the golden table."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "one_centre_ssss.txt")) if l.strip() and not l.startswith("#")]
+    s = _one_shell_sys([[0, 0, 0]], [0], [[1.0]])
+    s.P = np.array([[0.7]])
+    for om, val in rows:
+        J, K, _, _ = oracle.build_JK(s, tau=0.0, omega=float(om))
+        assert abs(J[0, 0] - 0.7 * float(val)) < 1e-15
+        assert abs(K[0, 0] - 0.7 * float(val)) < 1e-15
+
+
+def test_J_config0_brute_force():
+    s = hi.config0()
+    G = oracle.eri_tensor(s, omega=hi.OMEGA_HSE)
+    J, _, _, cnt = oracle.build_JK(s, tau=0.0, omega=hi.OMEGA_HSE)
+    assert np.abs(J - np.einsum("ijkl,kl->ij", G, s.P)).max() < 1e-13
+    assert cnt["quartets"] == 136 * 137 // 2
+
+
 def test_screening_error_bound():
     """K(tau) - K(0) is bounded by the dropped quartets' Schwarz bounds."""
     s = hi.config0()
