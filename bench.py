@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--mixed-cut", type=float, default=1e-7, help="tuned FP32 cut on Q_IJ Q_KL")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
+    ap.add_argument("--no-jk", action="store_true", help="skip the Coulomb + exchange leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
     ap.add_argument("--batch-natom", type=str, default="6,20",
                     help="atom-count range of the batched systems (scaled-down config-3 recipe)")
@@ -452,6 +453,24 @@ def main():
             "fp32_quartet_fraction": stm["quartets_fp32"] / max(1, stm["quartets"]),
             "max_abs_dK_vs_fp64_gpu": float(np.abs(Kmh - Kh).max()),
             "trPK_err_vs_fp64_gpu": float(abs(np.sum(Ph * Kmh) - np.sum(Ph * Kh))),
+        }
+    if not a.no_jk:
+        # Coulomb J digested from the same quartets (FP64): cost over K alone
+        Jj, Kj = torch.empty_like(P), torch.empty_like(P)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stj = hfx.build_JK_shard(pairs, P, Jj, Kj, o, a.shard, a.shards, stats=True)
+        torch.cuda.synchronize()
+        tj = time.perf_counter() - t0
+        print(f"# J+K step: {tj:.3f} s", file=sys.stderr, flush=True)
+        Jh = Jj.cpu().numpy()
+        out["coulomb_and_exchange"] = {
+            "value": stj["quartets"] / tj,
+            "unit": "quartets/s",
+            "ms_per_step": 1e3 * tj,
+            "time_vs_exchange_only": (1e3 * tj) / ms,
+            "max_abs_dK_vs_exchange_only": float(np.abs(Kj.cpu().numpy() - Kh).max()),
+            "J_symmetric": bool(np.abs(Jh - Jh.T).max() == 0.0),
         }
     if not a.no_batch:
         out["batched"] = batch_leg(a, hfx, hi, torch)

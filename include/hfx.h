@@ -141,6 +141,17 @@ hfx_status hfx_schwarz_bounds(hfx_pairs p, const hfx_opts *o, double *q_host_or_
 hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
                        const hfx_opts *o, void *stream, hfx_stats *st_or_null);
 
+/* Coulomb and exchange from the same screened quartets: J_ij = sum_kl
+ * (ij|kl) P_kl (the Hartree term of the total-energy expression, Sec. 2)
+ * is digested from every quartet value that also feeds K (1), so the
+ * integrals are evaluated once for both.  J_dev, K_dev: device, n_bf x n_bf,
+ * leading dimension ld, both overwritten; J must alias neither P nor K.
+ * Screening, precision modes and stats are those of hfx_build_K (stats
+ * flops include the Coulomb digestion).  Errors: as hfx_build_K, EINVAL if
+ * J_dev is NULL or aliases P or K. */
+hfx_status hfx_build_JK(hfx_pairs p, const double *P_dev, double *J_dev, double *K_dev, int64_t ld,
+                        const hfx_opts *o, void *stream, hfx_stats *st_or_null);
+
 /* One device's share of the exchange build when it is distributed over
  * nshards devices: the bra pairs of every class (slots of the Q-sorted
  * lists) are dealt round-robin, slot s going to shard s mod nshards, and
@@ -153,6 +164,15 @@ hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_dev, int64_t 
 hfx_status hfx_build_K_shard(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
                              const hfx_opts *o, int32_t shard, int32_t nshards, void *stream,
                              hfx_stats *st_or_null);
+
+/* One device's share of the joint Coulomb + exchange build: the shard of
+ * hfx_build_K_shard with the Coulomb digestion of hfx_build_JK.  J and K
+ * receive that share's symmetrised partial matrices; the sums over shards
+ * are the J and K of hfx_build_JK.  Errors: as hfx_build_JK and
+ * hfx_build_K_shard. */
+hfx_status hfx_build_JK_shard(hfx_pairs p, const double *P_dev, double *J_dev, double *K_dev, int64_t ld,
+                              const hfx_opts *o, int32_t shard, int32_t nshards, void *stream,
+                              hfx_stats *st_or_null);
 
 /* Many independent systems in one persistent launch per pass, fed by a
  * device work queue (Sec. 5 proposes dynamic distribution of the quartet

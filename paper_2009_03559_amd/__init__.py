@@ -26,7 +26,9 @@ _PAIR_L = ["00", "10", "11", "20", "21", "22"]
 CLASS_TAGS = [_PAIR_L[b] + _PAIR_L[k] for b in range(6) for k in range(b + 1)]
 
 # Symbols declared in include/hfx.h.
-EXPORTS = ["hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_K_shard", "hfx_build_K_batch",
+EXPORTS = ["hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_JK", "hfx_build_JK_shard",
+           "hfx_build_K_shard",
+           "hfx_build_K_batch",
            "hfx_server_create", "hfx_submit", "hfx_poll", "hfx_pairs_nbf", "hfx_pairs_npair",
            "hfx_pairs_device_bytes", "hfx_eval_quartets", "hfx_pairs_destroy", "hfx_server_destroy",
            "hfx_last_error"]
@@ -78,6 +80,9 @@ def lib():
                                             ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
         L.hfx_schwarz_bounds.argtypes = [vp, ctypes.POINTER(Opts), vp, vp]
         L.hfx_build_K.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(Opts), vp, ctypes.POINTER(Stats)]
+        L.hfx_build_JK.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.POINTER(Opts), vp, ctypes.POINTER(Stats)]
+        L.hfx_build_JK_shard.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.POINTER(Opts), ctypes.c_int32,
+                                         ctypes.c_int32, vp, ctypes.POINTER(Stats)]
         L.hfx_build_K_shard.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(Opts), ctypes.c_int32,
                                         ctypes.c_int32, vp, ctypes.POINTER(Stats)]
         L.hfx_build_K_batch.argtypes = [ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp,
@@ -93,7 +98,9 @@ def lib():
         L.hfx_pairs_destroy.restype = None
         L.hfx_server_destroy.argtypes = [vp]
         L.hfx_server_destroy.restype = None
-        for f in ("hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_K_shard", "hfx_build_K_batch",
+        for f in ("hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_JK", "hfx_build_JK_shard",
+                  "hfx_build_K_shard",
+                  "hfx_build_K_batch",
                   "hfx_server_create", "hfx_submit", "hfx_poll", "hfx_eval_quartets"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -191,6 +198,29 @@ def build_K(p: Pairs, P, K, o: Opts, stream=None, stats=False):
     st = Stats() if stats else None
     _check(lib().hfx_build_K(p.handle, _ptr(P), _ptr(K), ld, ctypes.byref(o), _stream_ptr(stream),
                              ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def build_JK(p: Pairs, P, J, K, o: Opts, stream=None, stats=False):
+    """Coulomb J and exchange K from the same quartets.  P, J, K: device
+    tensors (n_bf x n_bf float64) with one leading dimension."""
+    ld = int(P.stride(0))
+    if int(K.stride(0)) != ld or int(J.stride(0)) != ld:
+        raise HfxError(HFX_EINVAL, "P, J and K must share the leading dimension")
+    st = Stats() if stats else None
+    _check(lib().hfx_build_JK(p.handle, _ptr(P), _ptr(J), _ptr(K), ld, ctypes.byref(o), _stream_ptr(stream),
+                              ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def build_JK_shard(p: Pairs, P, J, K, o: Opts, shard: int, nshards: int, stream=None, stats=False):
+    """One shard's symmetrised partial J and K."""
+    ld = int(P.stride(0))
+    if int(K.stride(0)) != ld or int(J.stride(0)) != ld:
+        raise HfxError(HFX_EINVAL, "P, J and K must share the leading dimension")
+    st = Stats() if stats else None
+    _check(lib().hfx_build_JK_shard(p.handle, _ptr(P), _ptr(J), _ptr(K), ld, ctypes.byref(o), int(shard),
+                                    int(nshards), _stream_ptr(stream), ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
 
 

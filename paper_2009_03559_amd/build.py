@@ -42,9 +42,12 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
                            "--model", os.path.join(GEN, "model.json")])
     srcs = sorted(os.path.join(GEN, f) for f in os.listdir(GEN) if f.endswith(".hip"))
     srcs += [os.path.join(CSRC, f) for f in ("hfx_host.hip", "hfx_serve.hip")]
-    # largest classes first so the pool finishes together
-    srcs.sort(key=lambda s: -os.path.getsize(s.replace("tu_", "eri_").replace(".hip", ".h"))
-              if os.path.exists(s.replace("tu_", "eri_").replace(".hip", ".h")) else 0)
+    # largest classes first so the pool finishes together (a class's
+    # Coulomb-digesting variant shares its header)
+    def header(src):
+        return src.replace("tu_", "eri_").replace("_jk.hip", ".hip").replace(".hip", ".h")
+
+    srcs.sort(key=lambda s: -os.path.getsize(header(s)) if os.path.exists(header(s)) else 0)
     jobs = jobs or min(16, os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(jobs) as ex:

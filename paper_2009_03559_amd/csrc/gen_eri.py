@@ -342,8 +342,11 @@ def emit_post(em, la, lb, lc, ld, name="post"):
     return flops
 
 
-def emit_digest_part(em, la, lb, lc, ld, name, f_part):
+def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
     """Streaming digestion of one slice of the contracted array.
+
+    mode "K": exchange (below).  mode "J": the Coulomb digestion of the same
+    shares, J'_ab += 2 d v P_cd and J'_cd += 2 d v P_ab (J = J' + J'^T).
 
     acc holds [e|f] for every bra e (la..la+lb) and the ket components f in
     `f_part` (layout e-major).  The bra horizontal recurrence and spherical
@@ -366,6 +369,14 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part):
     L.append(f"      double deg, const double* __restrict__ P, double* K, int64_t ld) {{")
     brec, border = hrr_plan(la, lb)
     krec, korder = hrr_plan(lc, ld)
+    jtouched = set()
+    if mode == "J":
+        # K is the Coulomb matrix here; P_cd of the ket pair is read once
+        L.append("    const double deg2 = 2.0 * deg;")
+        for cs in range(ncs):
+            for ds in range(nds):
+                L.append(f"    const double pcd{cs}_{ds} = P[(int64_t)(c0 + {cs}) * ld + d0 + {ds}];")
+                L.append(f"    double jcd{cs}_{ds} = 0.0;")
     # bra HRR + spherical for every f of the slice
     for jf, f in enumerate(f_part):
         names = {}
@@ -388,14 +399,16 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part):
                         terms.append(nm if c == 1.0 else f"{em.lit(c)} * {nm}")
                 L.append(f"    const {T} s{as_}_{bs}_{jf} = " + " + ".join(terms) + ";")
     # ket HRR + spherical with the missing f as structural zeros, then digestion
-    for bs in range(nbs):
-        for ks in ("c", "d"):
-            n = ncs if ks == "c" else nds
-            for x in range(n):
-                L.append(f"    double kb{ks}{bs}_{x} = 0.0;")
+    if mode == "K":
+        for bs in range(nbs):
+            for ks in ("c", "d"):
+                n = ncs if ks == "c" else nds
+                for x in range(n):
+                    L.append(f"    double kb{ks}{bs}_{x} = 0.0;")
     for as_ in range(nas):
         L.append(f"    {{ const double* Pa = P + (int64_t)(a0 + {as_}) * ld;")
-        L.append("      double kac[%d] = {0}; double kad[%d] = {0};" % (ncs, nds))
+        if mode == "K":
+            L.append("      double kac[%d] = {0}; double kad[%d] = {0};" % (ncs, nds))
         for bs in range(nbs):
             L.append(f"      {{ const double* Pb = P + (int64_t)(b0 + {bs}) * ld;")
             names = {}
@@ -432,6 +445,17 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part):
                         v = f"v{as_}_{bs}_{cs}_{ds}"
                         L.append(f"        const double {v} = " + " + ".join(terms) + ";")
                         vals[(cs, ds)] = v
+            if mode == "J":
+                if vals:
+                    L.append(f"        const double pab = Pa[b0 + {bs}];")
+                    L.append("        const double jab = " + " + ".join(
+                        f"{vals[k]} * pcd{k[0]}_{k[1]}" for k in sorted(vals)) + ";")
+                    L.append(f"        atomicAdd(&K[(int64_t)(a0 + {as_}) * ld + b0 + {bs}], deg2 * jab);")
+                    for (cs, ds) in sorted(vals):
+                        L.append(f"        jcd{cs}_{ds} += {vals[(cs, ds)]} * pab;")
+                        jtouched.add((cs, ds))
+                L.append("      }")
+                continue
             for cs in range(ncs):
                 t1 = [f"{vals[(cs, ds)]} * Pb[d0 + {ds}]" for ds in range(nds) if (cs, ds) in vals]
                 t2 = [f"{vals[(cs, ds)]} * Pa[d0 + {ds}]" for ds in range(nds) if (cs, ds) in vals]
@@ -445,10 +469,20 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part):
                     L.append(f"        kad[{ds}] += " + " + ".join(t1) + ";")
                     L.append(f"        kbd{bs}_{ds} += " + " + ".join(t2) + ";")
             L.append("      }")
+        if mode == "J":
+            L.append("    }")
+            continue
         L.append(f"      double* Ka = K + (int64_t)(a0 + {as_}) * ld;")
         L.append(f"      for (int x = 0; x < {ncs}; ++x) atomicAdd(&Ka[c0 + x], deg * kac[x]);")
         L.append(f"      for (int x = 0; x < {nds}; ++x) atomicAdd(&Ka[d0 + x], deg * kad[x]);")
         L.append("    }")
+    if mode == "J":
+        for cs in range(ncs):
+            for ds in range(nds):
+                if (cs, ds) in jtouched:
+                    L.append(f"    atomicAdd(&K[(int64_t)(c0 + {cs}) * ld + d0 + {ds}], deg2 * jcd{cs}_{ds});")
+        L.append("  }")
+        return
     for bs in range(nbs):
         L.append(f"    {{ double* Kb = K + (int64_t)(b0 + {bs}) * ld;")
         for cs in range(ncs):
@@ -525,6 +559,26 @@ for _kv in filter(None, os.environ.get("HFX_WAVES", "").split(",")):
     WAVES[tuple(int(c) for c in _k)] = int(_v)
 
 
+def write_jk_tu(outdir, tag, suffix, nm, kernel, launcher):
+    """A translation unit of its own for the kernel that also digests the
+    Coulomb matrix (kept apart so the exchange-only kernel is unchanged)."""
+    tu = [
+        "// Generated by gen_eri.py; do not edit.",
+        '#include "hfx_device.hpp"',
+        f'#include "eri_{tag}{suffix}.h"',
+        "namespace hfx {",
+        f"void {launcher}_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
+        f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,  // 8 XCDs x chunk",
+        "                  [&](const QuartetArgs &a, unsigned grid) {",
+        f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME({kernel}<{nm}, true>), dim3(grid), dim3(64), 0, s, a);",
+        "                  });",
+        "}",
+        "}  // namespace hfx",
+    ]
+    with open(os.path.join(outdir, f"tu_{tag}{suffix}_jk.hip"), "w") as f:
+        f.write("\n".join(tu) + "\n")
+
+
 def class_tag(c):
     return "".join(str(x) for x in c)
 
@@ -563,6 +617,7 @@ def generate(outdir, T="double", splits=None):
             nacc_p.append(n_)
             split_cost.append(c)
             emit_digest_part(em, la, lb, lc, ld, f"dig_p{g}", ft)
+            emit_digest_part(em, la, lb, lc, ld, f"digJ_p{g}", ft, mode="J")
         em.lines.append(f"  static constexpr int NACCP[{G}] = {{{', '.join(str(x) for x in nacc_p)}}};")
         T_ = em.T
         em.lines.append("  template <int W> __device__ __forceinline__ static void vrr_p(const %s* __restrict__ g," % T_)
@@ -581,6 +636,14 @@ def generate(outdir, T="double", splits=None):
             kw = "if" if g_ == 0 else "else if"
             em.lines.append(f"    {kw} constexpr (W == {g_}) dig_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, a0, b0, c0, d0,"
                             " deg, P, K, ld);")
+        em.lines.append("  }")
+        em.lines.append("  template <int W> __device__ __forceinline__ static void digJ(const %s* __restrict__ acc," % T_)
+        em.lines.append("      %s ABx, %s ABy, %s ABz, %s CDx, %s CDy, %s CDz, int a0, int b0, int c0, int d0," % ((T_,) * 6))
+        em.lines.append("      double deg, const double* __restrict__ P, double* J, int64_t ld) {")
+        for g_ in range(G):
+            kw = "if" if g_ == 0 else "else if"
+            em.lines.append(f"    {kw} constexpr (W == {g_}) digJ_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, a0, b0, c0, d0,"
+                            " deg, P, J, ld);")
         em.lines.append("  }")
         pflops = emit_post(em, la, lb, lc, ld)
         em.lines.append("};")
@@ -610,6 +673,7 @@ def generate(outdir, T="double", splits=None):
             tu.append("}  // namespace hfx")
             with open(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "w") as f:
                 f.write("\n".join(tu) + "\n")
+            write_jk_tu(outdir, tag, suffix, nm, "k_eri32", "launch_erijk32")
             continue
         tu = [
             "// Generated by gen_eri.py; do not edit.",
@@ -646,6 +710,7 @@ def generate(outdir, T="double", splits=None):
         tu.append("}  // namespace hfx")
         with open(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "w") as f:
             f.write("\n".join(tu) + "\n")
+        write_jk_tu(outdir, tag, suffix, nm, "k_eri", "launch_erijk")
     return model
 
 

@@ -332,6 +332,7 @@ struct QuartetArgs {
     const float *boys32;
     const double *P;
     double *K;
+    double *J;                  // Coulomb J' of the same quartets, or null (exchange only)
     int64_t ld;
     unsigned long long *count;  // [0] quartets, [1] primitive quartets of this launch
 };
@@ -396,7 +397,7 @@ __device__ __forceinline__ int ket_cut(const QuartetArgs &a, int p, int g, int *
 // pair p in ket group g; each lane holds slice W of one quartet's contracted
 // array, accumulated over all primitive quartets, and digests that slice's
 // share of the quartet.
-template <class C, int W, int VRRW>
+template <class C, int W, int VRRW, bool WJ>
 __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, int lo, int cut) {
     const PairHdr bh = a.hdr[a.bra_ids[p]];
     const int nkp = a.ket_gnp[g];
@@ -440,17 +441,20 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
             if (bh.id == kh.id) deg *= 0.5;
             C::template dig<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB, kh.bfA,
                                kh.bfB, deg, a.P, a.K, a.ld);
+            if constexpr (WJ)
+                C::template digJ<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB,
+                                    kh.bfA, kh.bfB, deg, a.P, a.J, a.ld);
         }
     }
     if (W == 0 && a.count && nprim) atomicAdd(&a.count[1], nprim);
 }
 
-template <class C, int W>
+template <class C, int W, bool WJ = false>
 __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p, int g, int lo, int cut) {
     if (w == W) {
-        tile_part<C, W, W>(a, p, g, lo, cut);
+        tile_part<C, W, W, WJ>(a, p, g, lo, cut);
     } else if constexpr (W + 1 < C::NSPLIT) {
-        tile_dispatch<C, W + 1>(a, w, p, g, lo, cut);
+        tile_dispatch<C, W + 1, WJ>(a, w, p, g, lo, cut);
     }
 }
 
@@ -459,7 +463,8 @@ __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p
 // of ket components, each evaluated by its own wave (the waves of one tile
 // are adjacent block indices); the common part of the recurrence is
 // recomputed per slice instead of exchanged.
-template <class C>
+// WJ: also digest the Coulomb matrix J from the same quartet values.
+template <class C, bool WJ = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri(QuartetArgs a) {
     const int lb0 = xcd_block(a.nblk, 8 * C::NSPLIT);
     if (lb0 < 0) return;
@@ -478,12 +483,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     const int cut2 = min(cut, lo2 + a.tq);
     if (cut2 <= lo2) return;
     if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut2 - lo2));
-    tile_dispatch<C, 0>(a, w, p, g, lo2, cut2);
+    tile_dispatch<C, 0, WJ>(a, w, p, g, lo2, cut2);
 }
 
 // FP32 counterpart of tile_part: FP32 records, recurrences and contraction,
 // FP64 digestion into K.
-template <class C, int W>
+template <class C, int W, bool WJ>
 __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, int lo, int cut) {
     const PairHdr bh = a.hdr[a.bra_ids[p]];
     const int nkp = a.ket_gnp[g];
@@ -522,21 +527,26 @@ __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, 
             if (bh.id == kh.id) deg *= 0.5;
             C::template dig<W>(acc, (float)bh.ABx, (float)bh.ABy, (float)bh.ABz, (float)kh.ABx, (float)kh.ABy,
                                (float)kh.ABz, bh.bfA, bh.bfB, kh.bfA, kh.bfB, deg, a.P, a.K, a.ld);
+            if constexpr (WJ)
+                C::template digJ<W>(acc, (float)bh.ABx, (float)bh.ABy, (float)bh.ABz, (float)kh.ABx,
+                                    (float)kh.ABy, (float)kh.ABz, bh.bfA, bh.bfB, kh.bfA, kh.bfB, deg, a.P, a.J,
+                                    a.ld);
         }
     }
     if (W == 0 && a.count && nprim) atomicAdd(&a.count[1], nprim);
 }
 
-template <class C, int W>
+template <class C, int W, bool WJ = false>
 __device__ __forceinline__ void tile_dispatch32(const QuartetArgs &a, int w, int p, int g, int lo, int cut) {
     if (w == W) {
-        tile_part32<C, W>(a, p, g, lo, cut);
+        tile_part32<C, W, WJ>(a, p, g, lo, cut);
     } else if constexpr (W + 1 < C::NSPLIT) {
-        tile_dispatch32<C, W + 1>(a, w, p, g, lo, cut);
+        tile_dispatch32<C, W + 1, WJ>(a, w, p, g, lo, cut);
     }
 }
 
-template <class C>
+// WJ: also digest the Coulomb matrix J from the same quartet values.
+template <class C, bool WJ = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri32(QuartetArgs a) {
     const int lb0 = xcd_block(a.nblk, 8 * C::NSPLIT);
     if (lb0 < 0) return;
@@ -555,7 +565,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     const int cut2 = min(cut, lo2 + a.tq);
     if (cut2 <= lo2) return;
     if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut2 - lo2));
-    tile_dispatch32<C, 0>(a, w, p, g, lo2, cut2);
+    tile_dispatch32<C, 0, WJ>(a, w, p, g, lo2, cut2);
 }
 
 // ----------------------------------------------------------------------

@@ -232,7 +232,10 @@ __global__ void k_asym(const double *P, int64_t n, int64_t ld, double *part) {
                          const double *, double *, hipStream_t);
 HFX_FOR_CLASSES(DECL)
 #undef DECL
-#define DECL32(T) void launch_eri32_##T(const QuartetArgs &, unsigned, hipStream_t);
+#define DECL32(T)                                                           \
+    void launch_eri32_##T(const QuartetArgs &, unsigned, hipStream_t);     \
+    void launch_erijk_##T(const QuartetArgs &, unsigned, hipStream_t);     \
+    void launch_erijk32_##T(const QuartetArgs &, unsigned, hipStream_t);
 HFX_FOR_CLASSES(DECL32)
 #undef DECL32
 void launch_schwarz_00(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
@@ -262,6 +265,17 @@ static const eri_fn k_eri_tab[21] = {
 };
 static const eri_fn k_eri32_tab[21] = {
 #define E(T) launch_eri32_##T,
+    HFX_FOR_CLASSES(E)
+#undef E
+};
+// the same kernels digesting the Coulomb matrix as well
+static const eri_fn k_erijk_tab[21] = {
+#define E(T) launch_erijk_##T,
+    HFX_FOR_CLASSES(E)
+#undef E
+};
+static const eri_fn k_erijk32_tab[21] = {
+#define E(T) launch_erijk32_##T,
     HFX_FOR_CLASSES(E)
 #undef E
 };
@@ -640,7 +654,7 @@ const double *model_post();
 double model_prim_overhead(int op, int L);
 
 // Launch the quartet kernels of every class pair; K must already be zero.
-hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, const hfx_opts *o,
+hfx_status launch_classes(hfx_pairs p, const double *P, double *K, double *J, int64_t ld, const hfx_opts *o,
                           hipStream_t st, unsigned long long *count, int shard, int nshards,
                           hipEvent_t *ev) {
     const int op = kernel_op(o);
@@ -652,7 +666,7 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             const int ci = cb * (cb + 1) / 2 + ck;
             if (ev) HIPCHK(hipEventRecord(ev[ci], st));
             if (!B.n || !Kl.n || shard >= B.n) continue;
-            QuartetArgs a;
+            QuartetArgs a{};
             a.hdr = p->d_hdr;
             a.prim = p->d_prim;
             a.prim32 = p->d_prim32;
@@ -675,6 +689,7 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             a.boys32 = p->d_boys32;
             a.P = P;
             a.K = K;
+            a.J = J;
             a.ld = ld;
             // ket ranges are cut into sub-ranges of tq quartets so that no block
             // runs much longer than the others (quartet-block size per class)
@@ -690,14 +705,14 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, int64_t ld, c
             a.tau = mixed ? std::max(o->tau, o->mixed_cut) : o->tau;
             a.tau_hi = inf;
             a.count = count ? count + 4 * ci : nullptr;
-            k_eri_tab[ci](a, (unsigned)nblk, st);
+            (J ? k_erijk_tab : k_eri_tab)[ci](a, (unsigned)nblk, st);
             HIPCHK(hipGetLastError());
             if (mixed && o->mixed_cut > o->tau) {
                 // FP32: tau <= Q_p Q_q < cut
                 a.tau = o->tau;
                 a.tau_hi = o->mixed_cut;
                 a.count = count ? count + 4 * ci + 2 : nullptr;
-                k_eri32_tab[ci](a, (unsigned)nblk, st);
+                (J ? k_erijk32_tab : k_eri32_tab)[ci](a, (unsigned)nblk, st);
                 HIPCHK(hipGetLastError());
             }
         }
@@ -717,8 +732,13 @@ extern "C" hfx_status hfx_schwarz_bounds(hfx_pairs p, const hfx_opts *o, double 
     return HFX_OK;
 }
 
+static bool overlaps(const double *x, const double *y, int64_t n, int64_t ld) {
+    return x < y + (n - 1) * ld + n && y < x + (n - 1) * ld + n;
+}
+
 hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
-                             const hfx_opts *o, int shard, int nshards, void *stream, hfx_stats *st_out) {
+                             const hfx_opts *o, int shard, int nshards, void *stream, hfx_stats *st_out,
+                             double *J_dev) {
     auto t0 = std::chrono::steady_clock::now();
     if (!p) return fail(HFX_EINVAL, "pairs is NULL");
     if (!P_dev || !K_dev) return fail(HFX_EINVAL, "P or K is NULL");
@@ -727,8 +747,9 @@ hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, in
     if (s != HFX_OK) return s;
     const int64_t n = p->nbf;
     if (ld < n) return fail(HFX_EINVAL, "ld < n_bf");
-    if ((const double *)K_dev < P_dev + (n - 1) * ld + n && P_dev < (const double *)K_dev + (n - 1) * ld + n)
-        return fail(HFX_EINVAL, "K aliases P");
+    if (overlaps(K_dev, P_dev, n, ld)) return fail(HFX_EINVAL, "K aliases P");
+    if (J_dev && (overlaps(J_dev, P_dev, n, ld) || overlaps(J_dev, K_dev, n, ld)))
+        return fail(HFX_EINVAL, "J aliases P or K");
     hipStream_t st = (hipStream_t)stream;
     s = check_P(P_dev, n, ld, st);
     if (s != HFX_OK) return s;
@@ -744,14 +765,16 @@ hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, in
     unsigned long long *cnt = st_out ? p->d_count : nullptr;
     if (cnt) hipLaunchKernelGGL(k_fill_u64, dim3(2), dim3(64), 0, st, cnt, 4 * HFX_NCLASS);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, K_dev, n, ld);
+    if (J_dev) hipLaunchKernelGGL(k_fill, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, J_dev, n, ld);
     HIPCHK(hipGetLastError());
     hipEvent_t ev[HFX_NCLASS + 1] = {};
     if (st_out)
         for (auto &e : ev) HIPCHK(hipEventCreate(&e));
-    s = launch_classes(p, P_dev, K_dev, ld, o, st, cnt, shard, nshards, st_out ? ev : nullptr);
+    s = launch_classes(p, P_dev, K_dev, J_dev, ld, o, st, cnt, shard, nshards, st_out ? ev : nullptr);
     if (s != HFX_OK) return s;
     const unsigned g = (unsigned)((n + 15) / 16);
     hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(16, 16), 0, st, K_dev, n, ld);
+    if (J_dev) hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(16, 16), 0, st, J_dev, n, ld);
     HIPCHK(hipGetLastError());
     if (st_out) {
         std::vector<unsigned long long> h(4 * HFX_NCLASS);
@@ -772,7 +795,11 @@ hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, in
             st_out->class_device_s[c] = cm * 1e-3;
             const double nq = (double)(h[4 * c] + h[4 * c + 2]), npq = (double)(h[4 * c + 1] + h[4 * c + 3]);
             st_out->class_quartets[c] = (int64_t)(h[4 * c] + h[4 * c + 2]);
-            st_out->class_flops[c] = (mv[c] + model_prim_overhead(kernel_op(o), L)) * npq + mp[c] * nq;
+            // the Coulomb digestion adds two multiply-adds per spherical value
+            const double pj = J_dev ? 4.0 * (2 * PAIR_L[cb][0] + 1) * (2 * PAIR_L[cb][1] + 1) *
+                                          (2 * PAIR_L[ck][0] + 1) * (2 * PAIR_L[ck][1] + 1)
+                                    : 0.0;
+            st_out->class_flops[c] = (mv[c] + model_prim_overhead(kernel_op(o), L)) * npq + (mp[c] + pj) * nq;
             st_out->quartets += st_out->class_quartets[c];
             st_out->quartets_fp32 += (int64_t)h[4 * c + 2];
             st_out->prim_quartets += (int64_t)npq;
@@ -787,6 +814,19 @@ hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, in
 extern "C" hfx_status hfx_build_K(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
                                   const hfx_opts *o, void *stream, hfx_stats *st_out) {
     return build_K_impl(p, P_dev, K_dev, ld, o, 0, 1, stream, st_out);
+}
+
+extern "C" hfx_status hfx_build_JK(hfx_pairs p, const double *P_dev, double *J_dev, double *K_dev, int64_t ld,
+                                   const hfx_opts *o, void *stream, hfx_stats *st_out) {
+    if (!J_dev) return fail(HFX_EINVAL, "J is NULL");
+    return build_K_impl(p, P_dev, K_dev, ld, o, 0, 1, stream, st_out, J_dev);
+}
+
+extern "C" hfx_status hfx_build_JK_shard(hfx_pairs p, const double *P_dev, double *J_dev, double *K_dev,
+                                         int64_t ld, const hfx_opts *o, int32_t shard, int32_t nshards,
+                                         void *stream, hfx_stats *st_out) {
+    if (!J_dev) return fail(HFX_EINVAL, "J is NULL");
+    return build_K_impl(p, P_dev, K_dev, ld, o, shard, nshards, stream, st_out, J_dev);
 }
 
 extern "C" hfx_status hfx_build_K_shard(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,

@@ -29,7 +29,7 @@ hfx_status compute_bounds(hfx_pairs p, const hfx_opts *o, hipStream_t st);
 hfx_status build_lists(hfx_pairs p, double tau, hipStream_t st);
 hfx_status ensure_prim32(hfx_pairs p, hipStream_t st);
 hfx_status build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld, const hfx_opts *o,
-                        int shard, int nshards, void *stream, hfx_stats *st_out);
+                        int shard, int nshards, void *stream, hfx_stats *st_out, double *J_dev = nullptr);
 void launch_fill_K(double *K, int64_t n, int64_t ld, hipStream_t st);
 void launch_fill_u64(unsigned long long *c, int n, hipStream_t st);
 void launch_symmetrize(double *K, int64_t n, int64_t ld, hipStream_t st);
