@@ -406,11 +406,17 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
                 for x in range(n):
                     L.append(f"    double kb{ks}{bs}_{x} = 0.0;")
     for as_ in range(nas):
-        L.append(f"    {{ const double* Pa = P + (int64_t)(a0 + {as_}) * ld;")
+        if mode == "D":
+            L.append("    {")
+        else:
+            L.append(f"    {{ const double* Pa = P + (int64_t)(a0 + {as_}) * ld;")
         if mode == "K":
             L.append("      double kac[%d] = {0}; double kad[%d] = {0};" % (ncs, nds))
         for bs in range(nbs):
-            L.append(f"      {{ const double* Pb = P + (int64_t)(b0 + {bs}) * ld;")
+            if mode == "D":
+                L.append("      {")
+            else:
+                L.append(f"      {{ const double* Pb = P + (int64_t)(b0 + {bs}) * ld;")
             names = {}
             for k, n in enumerate(korder):
                 r = krec[n]
@@ -445,6 +451,12 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
                         v = f"v{as_}_{bs}_{cs}_{ds}"
                         L.append(f"        const double {v} = " + " + ".join(terms) + ";")
                         vals[(cs, ds)] = v
+            if mode == "D":
+                # Schwarz diagonal (ab|ab): K is the diagonal accumulator here
+                if (as_, bs) in vals:
+                    L.append(f"        K[{as_ * nbs + bs}] += {vals[(as_, bs)]};")
+                L.append("      }")
+                continue
             if mode == "J":
                 if vals:
                     L.append(f"        const double pab = Pa[b0 + {bs}];")
@@ -469,13 +481,16 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
                     L.append(f"        kad[{ds}] += " + " + ".join(t1) + ";")
                     L.append(f"        kbd{bs}_{ds} += " + " + ".join(t2) + ";")
             L.append("      }")
-        if mode == "J":
+        if mode in ("J", "D"):
             L.append("    }")
             continue
         L.append(f"      double* Ka = K + (int64_t)(a0 + {as_}) * ld;")
         L.append(f"      for (int x = 0; x < {ncs}; ++x) atomicAdd(&Ka[c0 + x], deg * kac[x]);")
         L.append(f"      for (int x = 0; x < {nds}; ++x) atomicAdd(&Ka[d0 + x], deg * kad[x]);")
         L.append("    }")
+    if mode == "D":
+        L.append("  }")
+        return
     if mode == "J":
         for cs in range(ncs):
             for ds in range(nds):
@@ -618,6 +633,8 @@ def generate(outdir, T="double", splits=None):
             split_cost.append(c)
             emit_digest_part(em, la, lb, lc, ld, f"dig_p{g}", ft)
             emit_digest_part(em, la, lb, lc, ld, f"digJ_p{g}", ft, mode="J")
+            if (la, lb) == (lc, ld):
+                emit_digest_part(em, la, lb, lc, ld, f"diag_p{g}", ft, mode="D")
         em.lines.append(f"  static constexpr int NACCP[{G}] = {{{', '.join(str(x) for x in nacc_p)}}};")
         T_ = em.T
         em.lines.append("  template <int W> __device__ __forceinline__ static void vrr_p(const %s* __restrict__ g," % T_)
@@ -637,6 +654,15 @@ def generate(outdir, T="double", splits=None):
             em.lines.append(f"    {kw} constexpr (W == {g_}) dig_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, a0, b0, c0, d0,"
                             " deg, P, K, ld);")
         em.lines.append("  }")
+        if (la, lb) == (lc, ld):
+            # share of slice W in the diagonal values (ab|ab), for the Schwarz factors
+            em.lines.append("  template <int W> __device__ __forceinline__ static void diag(const %s* __restrict__ acc," % T_)
+            em.lines.append("      %s ABx, %s ABy, %s ABz, double* __restrict__ d) {" % ((T_,) * 3))
+            for g_ in range(G):
+                kw = "if" if g_ == 0 else "else if"
+                em.lines.append(f"    {kw} constexpr (W == {g_}) diag_p{g_}(acc, ABx, ABy, ABz, ABx, ABy, ABz, 0, 0, 0, 0,"
+                                " 1.0, nullptr, d, 0);")
+            em.lines.append("  }")
         em.lines.append("  template <int W> __device__ __forceinline__ static void digJ(const %s* __restrict__ acc," % T_)
         em.lines.append("      %s ABx, %s ABy, %s ABz, %s CDx, %s CDy, %s CDz, int a0, int b0, int c0, int d0," % ((T_,) * 6))
         em.lines.append("      double deg, const double* __restrict__ P, double* J, int64_t ld) {")

@@ -630,7 +630,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     persist_loop<C, true>(jobs, njobs, vtotal, head, claim);
 }
 
-// Schwarz factor of each pair of one pair class: Q = sqrt(max diagonal (ij|ij)).
+// Slice W's share of the diagonal values (ab|ab) of pair h, then the next
+// slice: the slices of a split class run one after the other in one lane,
+// so only one slice's contracted array is live at a time.
+template <class C, int W>
+__device__ __forceinline__ void schwarz_slices(const PairHdr &h, const PrimRec *__restrict__ prim, int op,
+                                               double om2, const double *__restrict__ tab, double om,
+                                               double *diag) {
+    double acc[C::NACCP[W]];
+#pragma unroll
+    for (int i = 0; i < C::NACCP[W]; ++i) acc[i] = 0.0;
+    for (int kp = 0; kp < h.n; ++kp) {
+        const PrimRec k = prim[h.off + kp];
+        for (int bp = 0; bp < h.n; ++bp) {
+            const PrimRec b = prim[h.off + bp];
+            prim_quartet_p<C, W>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc, om);
+        }
+    }
+    C::template diag<W>(acc, h.ABx, h.ABy, h.ABz, diag);
+    if constexpr (W + 1 < C::NSPLIT) schwarz_slices<C, W + 1>(h, prim, op, om2, tab, om, diag);
+}
+
+// Schwarz factor of each pair of a pair class: Q = sqrt(max_ab (ab|ab)), the
+// diagonal class (IJ|IJ) evaluated slice by slice.
 template <class C>
 __global__ __launch_bounds__(64) void k_schwarz(const PairHdr *__restrict__ hdr,
                                                 const PrimRec *__restrict__ prim,
@@ -641,24 +663,14 @@ __global__ __launch_bounds__(64) void k_schwarz(const PairHdr *__restrict__ hdr,
     if (t >= n) return;
     const PairHdr h = hdr[ids[t]];
     const double om = sqrt(om2);
-    double acc[C::NACC];
-#pragma unroll
-    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
-    for (int kp = 0; kp < h.n; ++kp) {
-        const PrimRec k = prim[h.off + kp];
-        for (int bp = 0; bp < h.n; ++bp) {
-            const PrimRec b = prim[h.off + bp];
-            prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc, om);
-        }
-    }
-    double out[C::NOUT];
-    C::post(acc, h.ABx, h.ABy, h.ABz, h.ABx, h.ABy, h.ABz, out);
     constexpr int NA = 2 * C::LA + 1, NB = 2 * C::LB + 1;
+    double diag[NA * NB];
+#pragma unroll
+    for (int i = 0; i < NA * NB; ++i) diag[i] = 0.0;
+    schwarz_slices<C, 0>(h, prim, op, om2, tab, om, diag);
     double mx = 0.0;
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) mx = fmax(mx, out[((i * NB + j) * NA + i) * NB + j]);
+    for (int i = 0; i < NA * NB; ++i) mx = fmax(mx, diag[i]);
     Q[h.id] = sqrt(mx);
 }
 
