@@ -548,7 +548,7 @@ PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 # more slices recompute more of the shared recurrence.
 DEFAULT_SPLITS = {
     (2, 1, 1, 1): 2, (2, 1, 2, 0): 1, (2, 2, 1, 0): 1, (2, 2, 2, 0): 3,
-    (2, 1, 2, 1): 3, (2, 2, 1, 1): 3, (2, 2, 2, 1): 6, (2, 2, 2, 2): 12,
+    (2, 1, 2, 1): 3, (2, 2, 1, 1): 3, (2, 2, 2, 1): 5, (2, 2, 2, 2): 12,
 }
 
 # Override for tuning: HFX_SPLITS="2221:16,2222:32".
