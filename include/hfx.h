@@ -60,6 +60,7 @@ typedef enum { HFX_PREC_FP64 = 0, HFX_PREC_MIXED = 1 } hfx_prec;
 
 #define HFX_MAX_L 2
 #define HFX_MAX_PRIM 16
+#define HFX_MAX_NBF 65535 /* n_bf limit: n_bf^2 work-items per element kernel */
 #define HFX_NCLASS 21
 
 /* One contracted shell: centre index, angular momentum, primitive count and
@@ -118,7 +119,7 @@ typedef struct {
  * nshell entries.  exps, coefs: host, indexed by prim_off.  o: only checked
  * for validity here.  Errors: EINVAL (natom/nshell < 1, atom index, nprim
  * < 1, alpha <= 0 or not finite, offsets out of range), EUNSUPPORTED (l > 2,
- * nprim > HFX_MAX_PRIM), ENOMEM, EDEVICE.  On success *out owns the device
+ * nprim > HFX_MAX_PRIM, n_bf > HFX_MAX_NBF), ENOMEM, EDEVICE.  On success *out owns the device
  * memory until hfx_pairs_destroy. */
 hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, const hfx_shell *shells,
                                  int32_t nshell, const double *exps, const double *coefs,

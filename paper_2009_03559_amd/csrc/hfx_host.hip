@@ -400,6 +400,9 @@ extern "C" hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, co
     P->bfo[0] = 0;
     for (int s = 0; s < nshell; ++s) P->bfo[s + 1] = P->bfo[s] + 2 * shells[s].l + 1;
     P->nbf = P->bfo[nshell];
+    // n_bf^2 element kernels (fill, symmetrisation) index one work-item per
+    // element: the dispatch counts work-items in 32 bits
+    if (P->nbf > HFX_MAX_NBF) return fail(HFX_EUNSUPPORTED, "more than 65535 basis functions");
     const int64_t npair = (int64_t)nshell * (nshell + 1) / 2;
     P->npair = npair;
     std::vector<PairHdr> hdr(npair);

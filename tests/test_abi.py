@@ -52,6 +52,22 @@ def test_invalid_basis_rejected_on_host(mutate, status):
     assert e.value.status == status
 
 
+def test_too_many_functions_rejected_on_host():
+    """n_bf above HFX_MAX_NBF (65535): the n_bf^2 element kernels would pass
+    the 32-bit work-item count of one dispatch."""
+    natom = 13108  # one d shell each: 65540 functions
+    xyz = np.zeros((natom, 3))
+    xyz[:, 0] = 4.0 * np.arange(natom)
+    atom = np.arange(natom, dtype=np.int32)
+    ls = np.full(natom, 2, dtype=np.int32)
+    npr = np.ones(natom, dtype=np.int32)
+    off = np.arange(natom, dtype=np.int32)
+    ex = np.ones(natom)
+    with pytest.raises(hfx.HfxError) as e:
+        hfx.build_shell_pairs(xyz, atom, ls, npr, off, ex, np.ones(natom), o=hfx.opts(), stream=0)
+    assert e.value.status == hfx.HFX_EUNSUPPORTED
+
+
 @pytest.mark.parametrize("kw,status", [
     (dict(tau=-1.0), hfx.HFX_EINVAL),
     (dict(omega=-0.1, op=hfx.OP_ERFC), hfx.HFX_EINVAL),

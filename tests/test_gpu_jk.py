@@ -99,3 +99,53 @@ def test_JK_rejects_aliasing():
         with pytest.raises(hfx.HfxError) as e:
             hfx.build_JK(p, P, J, K, o)
         assert e.value.status == hfx.HFX_EINVAL
+
+
+@pytest.mark.parametrize("nshards", [3, 7])
+def test_shards_sum_to_full_build(nshards):
+    """hfx_build_K_shard / hfx_build_JK_shard: the bra slots of every class are
+    dealt round-robin; the symmetrised partial matrices of all shards add up
+    to the single-device J and K, and the quartet counts add up too."""
+    s = hi.lattice_system(8, seed=23, nprim_range=(1, 3))
+    o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
+    p = hfx.pairs_from_system(s, o)
+    P = torch.from_numpy(s.P).cuda()
+    J, K = torch.empty_like(P), torch.empty_like(P)
+    st = hfx.build_JK(p, P, J, K, o, stats=True)
+    Js, Ks = torch.zeros_like(P), torch.zeros_like(P)
+    Kk = torch.zeros_like(P)
+    nq = 0
+    for sh in range(nshards):
+        Jp, Kp = torch.empty_like(P), torch.empty_like(P)
+        nq += hfx.build_JK_shard(p, P, Jp, Kp, o, sh, nshards, stats=True)["quartets"]
+        Js += Jp
+        Ks += Kp
+        K1 = torch.empty_like(P)
+        hfx.build_K_shard(p, P, K1, o, sh, nshards)
+        Kk += K1
+    torch.cuda.synchronize()
+    assert nq == st["quartets"]
+    assert torch.abs(Js - J).max().item() <= 1e-12 * max(1.0, torch.abs(J).max().item())
+    assert torch.abs(Ks - K).max().item() <= 1e-12 * max(1.0, torch.abs(K).max().item())
+    assert torch.abs(Kk - K).max().item() <= 1e-12 * max(1.0, torch.abs(K).max().item())
+    with pytest.raises(hfx.HfxError) as e:
+        hfx.build_K_shard(p, P, Kk, o, nshards, nshards)
+    assert e.value.status == hfx.HFX_EINVAL
+
+
+def test_JK_leading_dimension():
+    s = hi.config0()
+    n = s.nbf
+    big = torch.zeros((n, n + 5), dtype=torch.float64, device="cuda")
+    big[:, :n] = torch.from_numpy(s.P).cuda()
+    Jb = torch.full((n, n + 5), 3.0, dtype=torch.float64, device="cuda")
+    Kb = torch.full((n, n + 5), 7.0, dtype=torch.float64, device="cuda")
+    o = hfx.opts(omega=0.11)
+    p = hfx.pairs_from_system(s, o)
+    hfx.build_JK(p, big[:, :n], Jb[:, :n], Kb[:, :n], o)
+    torch.cuda.synchronize()
+    Jo, Ko, _, _ = oracle.build_JK(s, tau=1e-10, omega=0.11)
+    Jg, Kg = Jb.cpu().numpy(), Kb.cpu().numpy()
+    assert np.abs(Jg[:, :n] - Jo).max() <= 1e-10
+    assert np.abs(Kg[:, :n] - Ko).max() <= 1e-10
+    assert (Jg[:, n:] == 3.0).all() and (Kg[:, n:] == 7.0).all()
