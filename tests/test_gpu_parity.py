@@ -274,3 +274,33 @@ def test_full_size_config1_sampled():
         ref = oracle.shell_quartet(s, *qq, omega=hi.OMEGA_HSE)
         bound = q[_pid(qq[0], qq[1])] * q[_pid(qq[2], qq[3])]
         assert np.abs(g - ref).max() <= 1e-12 * bound + 1e-300
+
+
+def test_full_size_bench_shard_properties():
+    """The bench's launch configuration (256-atom system, shard 0 of 64, erfc,
+    tau = 1e-10): K is linear in P (K(P + 2E) = K(P) + 2 K(E) for a
+    symmetric E, so no P-dependent work is skipped and no update is lost or
+    doubled between runs), exactly symmetric, and zero for P = 0."""
+    s = hi.config1()
+    o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
+    p = hfx.pairs_from_system(s, o)
+    P = torch.from_numpy(s.P).cuda()
+    rng = np.random.default_rng(77)
+    E = rng.standard_normal(s.P.shape) * (s.P != 0)
+    E = torch.from_numpy(0.5 * (E + E.T)).cuda()
+    Ks = []
+    for X in (P, E, P + 2.0 * E):
+        _say("bench shard build, 256 atoms, shard 0/64")
+        K = torch.empty_like(P)
+        hfx.build_K_shard(p, X.contiguous(), K, o, 0, 64)
+        torch.cuda.synchronize()
+        Ks.append(K)
+    scale = max(torch.abs(Ks[0]).max().item(), torch.abs(Ks[1]).max().item())
+    assert torch.abs(Ks[2] - Ks[0] - 2.0 * Ks[1]).max().item() <= 1e-12 * scale
+    for K in Ks:
+        assert torch.equal(K, K.T)
+    Z = torch.zeros_like(P)
+    K0 = torch.empty_like(P)
+    hfx.build_K_shard(p, Z, K0, o, 0, 64)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(K0).item() == 0
