@@ -574,7 +574,7 @@ for _kv in filter(None, os.environ.get("HFX_WAVES", "").split(",")):
     WAVES[tuple(int(c) for c in _k)] = int(_v)
 
 
-def write_jk_tu(outdir, tag, suffix, nm, kernel, launcher):
+def write_jk_tu(outdir, tag, suffix, nm, kernel, launcher, swap="false"):
     """A translation unit of its own for the kernel that also digests the
     Coulomb matrix (kept apart so the exchange-only kernel is unchanged)."""
     tu = [
@@ -585,7 +585,7 @@ def write_jk_tu(outdir, tag, suffix, nm, kernel, launcher):
         f"void {launcher}_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
         f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,  // 8 XCDs x chunk",
         "                  [&](const QuartetArgs &a, unsigned grid) {",
-        f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME({kernel}<{nm}, true>), dim3(grid), dim3(64), 0, s, a);",
+        f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME({kernel}<{nm}, true{', true' if swap == 'true' else ''}>), dim3(grid), dim3(64), 0, s, a);",
         "                  });",
         "}",
         "}  // namespace hfx",
@@ -594,8 +594,94 @@ def write_jk_tu(outdir, tag, suffix, nm, kernel, launcher):
         f.write("\n".join(tu) + "\n")
 
 
+# Classes evaluated with the roles of the pairs exchanged, (cd|ab) in place of
+# (ab|cd), so that the slices split the components of the original bra pair
+# (for these classes the recurrence shared between slices is smaller that way),
+# with the slice counts of the exchanged class.  The digestion images are then
+# the transposes of the usual ones, which K = K' + K'^T absorbs.  FP64 direct
+# launches only.  Measured on the 256-atom shard: (dp|pp) -8 %, (dd|pp) -7 %,
+# (dd|ds) -4 %; (dd|dp) exchanged spills to scratch and stays as it is.
+# HFX_TRANSPOSED="2111:2,2211:3" overrides (tuning); "none" turns it off.
+TRANSPOSED = {(2, 1, 1, 1): 2, (2, 2, 1, 1): 3, (2, 2, 2, 0): 2}
+_tr = os.environ.get("HFX_TRANSPOSED", "")
+if _tr == "none":
+    TRANSPOSED = {}
+if _tr != "none":
+    for _kv in filter(None, _tr.split(",")):
+        _k, _v = _kv.split(":")
+        TRANSPOSED[tuple(int(c) for c in _k)] = int(_v)
+
+
 def class_tag(c):
     return "".join(str(x) for x in c)
+
+
+def emit_struct(em, la, lb, lc, ld, nm, G):
+    """One class struct: the unsplit recurrence, the G ket-component slices
+    (recurrence, exchange and Coulomb digestion, Schwarz diagonal of diagonal
+    classes) and the unsplit post-processing.  Returns the model figures."""
+    E, F = la + lb, lc + ld
+    NE = sum(ncart(d) for d in range(la, E + 1))
+    NF = sum(ncart(d) for d in range(lc, F + 1))
+    em.lines.append(f"struct {nm} {{")
+    em.lines.append(f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {E + F};")
+    em.lines.append(f"  static constexpr int NE = {NE}, NF = {NF}, NACC = {NE * NF};")
+    nsph = (2 * la + 1) * (2 * lb + 1) * (2 * lc + 1) * (2 * ld + 1)
+    em.lines.append(f"  static constexpr int NOUT = {nsph};")
+    _, vflops = emit_vrr(em, la, lb, lc, ld, "vrr")
+    G = min(G, NF)  # no empty slices
+    em.lines.append(f"  static constexpr int NSPLIT = {G};")
+    em.lines.append(f"  static constexpr int WAVES = {WAVES.get((la, lb, lc, ld), 1)};")
+    split_cost = []
+    groups = best_split(la, lb, lc, ld, G) if G > 1 else [[f for d in range(lc, F + 1) for f in cart(d)]]
+    nacc_p = []
+    for g, ft in enumerate(groups):
+        n_, c = emit_vrr(em, la, lb, lc, ld, f"vrr_p{g}", f_targets=ft)
+        nacc_p.append(n_)
+        split_cost.append(c)
+        emit_digest_part(em, la, lb, lc, ld, f"dig_p{g}", ft)
+        emit_digest_part(em, la, lb, lc, ld, f"digJ_p{g}", ft, mode="J")
+        if (la, lb) == (lc, ld):
+            emit_digest_part(em, la, lb, lc, ld, f"diag_p{g}", ft, mode="D")
+    em.lines.append(f"  static constexpr int NACCP[{G}] = {{{', '.join(str(x) for x in nacc_p)}}};")
+    T_ = em.T
+    em.lines.append("  template <int W> __device__ __forceinline__ static void vrr_p(const %s* __restrict__ g," % T_)
+    em.lines.append("      %s PAx, %s PAy, %s PAz, %s WPx, %s WPy, %s WPz," % ((T_,) * 6))
+    em.lines.append("      %s QCx, %s QCy, %s QCz, %s WQx, %s WQy, %s WQz," % ((T_,) * 6))
+    em.lines.append("      %s i2z, %s roz, %s i2e, %s roe, %s i2ze, %s* __restrict__ acc) {" % ((T_,) * 6))
+    for g_ in range(G):
+        kw = "if" if g_ == 0 else "else if"
+        em.lines.append(f"    {kw} constexpr (W == {g_}) vrr_p{g_}(g, PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz,"
+                        " WQx, WQy, WQz, i2z, roz, i2e, roe, i2ze, acc);")
+    em.lines.append("  }")
+    em.lines.append("  template <int W> __device__ __forceinline__ static void dig(const %s* __restrict__ acc," % T_)
+    em.lines.append("      %s ABx, %s ABy, %s ABz, %s CDx, %s CDy, %s CDz, int a0, int b0, int c0, int d0," % ((T_,) * 6))
+    em.lines.append("      double deg, const double* __restrict__ P, double* K, int64_t ld) {")
+    for g_ in range(G):
+        kw = "if" if g_ == 0 else "else if"
+        em.lines.append(f"    {kw} constexpr (W == {g_}) dig_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, a0, b0, c0, d0,"
+                        " deg, P, K, ld);")
+    em.lines.append("  }")
+    if (la, lb) == (lc, ld):
+        # share of slice W in the diagonal values (ab|ab), for the Schwarz factors
+        em.lines.append("  template <int W> __device__ __forceinline__ static void diag(const %s* __restrict__ acc," % T_)
+        em.lines.append("      %s ABx, %s ABy, %s ABz, double* __restrict__ d) {" % ((T_,) * 3))
+        for g_ in range(G):
+            kw = "if" if g_ == 0 else "else if"
+            em.lines.append(f"    {kw} constexpr (W == {g_}) diag_p{g_}(acc, ABx, ABy, ABz, ABx, ABy, ABz, 0, 0, 0, 0,"
+                            " 1.0, nullptr, d, 0);")
+        em.lines.append("  }")
+    em.lines.append("  template <int W> __device__ __forceinline__ static void digJ(const %s* __restrict__ acc," % T_)
+    em.lines.append("      %s ABx, %s ABy, %s ABz, %s CDx, %s CDy, %s CDz, int a0, int b0, int c0, int d0," % ((T_,) * 6))
+    em.lines.append("      double deg, const double* __restrict__ P, double* J, int64_t ld) {")
+    for g_ in range(G):
+        kw = "if" if g_ == 0 else "else if"
+        em.lines.append(f"    {kw} constexpr (W == {g_}) digJ_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, a0, b0, c0, d0,"
+                        " deg, P, J, ld);")
+    em.lines.append("  }")
+    pflops = emit_post(em, la, lb, lc, ld)
+    em.lines.append("};")
+    return vflops, pflops, NE, NF, nsph, G, split_cost
 
 
 def generate(outdir, T="double", splits=None):
@@ -615,64 +701,12 @@ def generate(outdir, T="double", splits=None):
         NE = sum(ncart(d) for d in range(la, E + 1))
         NF = sum(ncart(d) for d in range(lc, F + 1))
         nm = f"Eri{tag}{suffix}"
-        em.lines.append(f"struct {nm} {{")
-        em.lines.append(f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {E + F};")
-        em.lines.append(f"  static constexpr int NE = {NE}, NF = {NF}, NACC = {NE * NF};")
-        nsph = (2 * la + 1) * (2 * lb + 1) * (2 * lc + 1) * (2 * ld + 1)
-        em.lines.append(f"  static constexpr int NOUT = {nsph};")
-        _, vflops = emit_vrr(em, la, lb, lc, ld, "vrr")
-        G = min(splits.get((la, lb, lc, ld), 1), NF)  # no empty slices
-        em.lines.append(f"  static constexpr int NSPLIT = {G};")
-        em.lines.append(f"  static constexpr int WAVES = {WAVES.get((la, lb, lc, ld), 1)};")
-        split_cost = []
-        groups = best_split(la, lb, lc, ld, G) if G > 1 else [[f for d in range(lc, F + 1) for f in cart(d)]]
-        nacc_p = []
-        for g, ft in enumerate(groups):
-            n_, c = emit_vrr(em, la, lb, lc, ld, f"vrr_p{g}", f_targets=ft)
-            nacc_p.append(n_)
-            split_cost.append(c)
-            emit_digest_part(em, la, lb, lc, ld, f"dig_p{g}", ft)
-            emit_digest_part(em, la, lb, lc, ld, f"digJ_p{g}", ft, mode="J")
-            if (la, lb) == (lc, ld):
-                emit_digest_part(em, la, lb, lc, ld, f"diag_p{g}", ft, mode="D")
-        em.lines.append(f"  static constexpr int NACCP[{G}] = {{{', '.join(str(x) for x in nacc_p)}}};")
-        T_ = em.T
-        em.lines.append("  template <int W> __device__ __forceinline__ static void vrr_p(const %s* __restrict__ g," % T_)
-        em.lines.append("      %s PAx, %s PAy, %s PAz, %s WPx, %s WPy, %s WPz," % ((T_,) * 6))
-        em.lines.append("      %s QCx, %s QCy, %s QCz, %s WQx, %s WQy, %s WQz," % ((T_,) * 6))
-        em.lines.append("      %s i2z, %s roz, %s i2e, %s roe, %s i2ze, %s* __restrict__ acc) {" % ((T_,) * 6))
-        for g_ in range(G):
-            kw = "if" if g_ == 0 else "else if"
-            em.lines.append(f"    {kw} constexpr (W == {g_}) vrr_p{g_}(g, PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz,"
-                            " WQx, WQy, WQz, i2z, roz, i2e, roe, i2ze, acc);")
-        em.lines.append("  }")
-        em.lines.append("  template <int W> __device__ __forceinline__ static void dig(const %s* __restrict__ acc," % T_)
-        em.lines.append("      %s ABx, %s ABy, %s ABz, %s CDx, %s CDy, %s CDz, int a0, int b0, int c0, int d0," % ((T_,) * 6))
-        em.lines.append("      double deg, const double* __restrict__ P, double* K, int64_t ld) {")
-        for g_ in range(G):
-            kw = "if" if g_ == 0 else "else if"
-            em.lines.append(f"    {kw} constexpr (W == {g_}) dig_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, a0, b0, c0, d0,"
-                            " deg, P, K, ld);")
-        em.lines.append("  }")
-        if (la, lb) == (lc, ld):
-            # share of slice W in the diagonal values (ab|ab), for the Schwarz factors
-            em.lines.append("  template <int W> __device__ __forceinline__ static void diag(const %s* __restrict__ acc," % T_)
-            em.lines.append("      %s ABx, %s ABy, %s ABz, double* __restrict__ d) {" % ((T_,) * 3))
-            for g_ in range(G):
-                kw = "if" if g_ == 0 else "else if"
-                em.lines.append(f"    {kw} constexpr (W == {g_}) diag_p{g_}(acc, ABx, ABy, ABz, ABx, ABy, ABz, 0, 0, 0, 0,"
-                                " 1.0, nullptr, d, 0);")
-            em.lines.append("  }")
-        em.lines.append("  template <int W> __device__ __forceinline__ static void digJ(const %s* __restrict__ acc," % T_)
-        em.lines.append("      %s ABx, %s ABy, %s ABz, %s CDx, %s CDy, %s CDz, int a0, int b0, int c0, int d0," % ((T_,) * 6))
-        em.lines.append("      double deg, const double* __restrict__ P, double* J, int64_t ld) {")
-        for g_ in range(G):
-            kw = "if" if g_ == 0 else "else if"
-            em.lines.append(f"    {kw} constexpr (W == {g_}) digJ_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, a0, b0, c0, d0,"
-                            " deg, P, J, ld);")
-        em.lines.append("  }")
-        pflops = emit_post(em, la, lb, lc, ld)
-        em.lines.append("};")
+        vflops, pflops, NE, NF, nsph, G, split_cost = emit_struct(
+            em, la, lb, lc, ld, nm, splits.get((la, lb, lc, ld), 1))
+        if T == "double" and (la, lb, lc, ld) in TRANSPOSED:
+            # the same integrals with the pairs' roles exchanged, sliced over
+            # the components of the original bra pair (see TRANSPOSED)
+            emit_struct(em, lc, ld, la, lb, nm + "T", TRANSPOSED[(la, lb, lc, ld)])
         with open(os.path.join(outdir, f"eri_{tag}{suffix}.h"), "w") as f:
             f.write("\n".join(em.lines) + "\n")
         model[tag] = dict(vrr_flops=vflops, post_flops=pflops, nacc=NE * NF,
@@ -701,15 +735,18 @@ def generate(outdir, T="double", splits=None):
                 f.write("\n".join(tu) + "\n")
             write_jk_tu(outdir, tag, suffix, nm, "k_eri32", "launch_erijk32")
             continue
+        # direct launches of a class in TRANSPOSED use the exchanged struct
+        tr = (la, lb, lc, ld) in TRANSPOSED
+        dn, sw = (nm + "T", "true") if tr else (nm, "false")
         tu = [
             "// Generated by gen_eri.py; do not edit.",
             '#include "hfx_device.hpp"',
             f'#include "eri_{tag}{suffix}.h"',
             "namespace hfx {",
             f"void launch_eri_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
-            f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,  // 8 XCDs x chunk",
+            f"  launch_segments(a0, (long long)nblk * {dn}::NSPLIT, 64ll * {dn}::NSPLIT,  // 8 XCDs x chunk",
             "                  [&](const QuartetArgs &a, unsigned grid) {",
-            f"                    hipLaunchKernelGGL(k_eri<{nm}>, dim3(grid), dim3(64), 0, s, a);",
+            f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri<{dn}, false, {sw}>), dim3(grid), dim3(64), 0, s, a);",
             "                  });",
             "}",
             f"void launch_persist_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
@@ -736,7 +773,7 @@ def generate(outdir, T="double", splits=None):
         tu.append("}  // namespace hfx")
         with open(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "w") as f:
             f.write("\n".join(tu) + "\n")
-        write_jk_tu(outdir, tag, suffix, nm, "k_eri", "launch_erijk")
+        write_jk_tu(outdir, tag, suffix, dn, "k_eri", "launch_erijk", sw)
     return model
 
 

@@ -397,7 +397,10 @@ __device__ __forceinline__ int ket_cut(const QuartetArgs &a, int p, int g, int *
 // pair p in ket group g; each lane holds slice W of one quartet's contracted
 // array, accumulated over all primitive quartets, and digests that slice's
 // share of the quartet.
-template <class C, int W, int VRRW, bool WJ>
+// SWAP: C is the class with the pairs' roles exchanged, (cd|ab): the lane's
+// ket record enters the recurrence as its bra and the wave's bra record as
+// its ket, and the digestion images are the transposes of the usual ones.
+template <class C, int W, int VRRW, bool WJ, bool SWAP>
 __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, int lo, int cut) {
     const PairHdr bh = a.hdr[a.bra_ids[p]];
     const int nkp = a.ket_gnp[g];
@@ -430,8 +433,12 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
                 const PrimRec b = load_rec(brec + bp);
                 if (!__any(kb * b.B >= eps)) break;
                 nprim += act;
-                prim_quartet_p<C, W>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, a.op, a.om2,
-                                     a.boys, acc, a.om);
+                if constexpr (SWAP)
+                    prim_quartet_p<C, W>(k, b.z, b.i2z, b.Px, b.Py, b.Pz, b.PAx, b.PAy, b.PAz, b.K, a.op, a.om2,
+                                         a.boys, acc, a.om);
+                else
+                    prim_quartet_p<C, W>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, a.op, a.om2,
+                                         a.boys, acc, a.om);
             }
         }
         if (act) {
@@ -439,22 +446,23 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
             if (bh.diag) deg *= 0.5;
             if (kh.diag) deg *= 0.5;
             if (bh.id == kh.id) deg *= 0.5;
-            C::template dig<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB, kh.bfA,
-                               kh.bfB, deg, a.P, a.K, a.ld);
+            const PairHdr &x = SWAP ? kh : bh, &y = SWAP ? bh : kh;
+            C::template dig<W>(acc, x.ABx, x.ABy, x.ABz, y.ABx, y.ABy, y.ABz, x.bfA, x.bfB, y.bfA, y.bfB, deg,
+                               a.P, a.K, a.ld);
             if constexpr (WJ)
-                C::template digJ<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB,
-                                    kh.bfA, kh.bfB, deg, a.P, a.J, a.ld);
+                C::template digJ<W>(acc, x.ABx, x.ABy, x.ABz, y.ABx, y.ABy, y.ABz, x.bfA, x.bfB, y.bfA,
+                                    y.bfB, deg, a.P, a.J, a.ld);
         }
     }
     if (W == 0 && a.count && nprim) atomicAdd(&a.count[1], nprim);
 }
 
-template <class C, int W, bool WJ = false>
+template <class C, int W, bool WJ = false, bool SWAP = false>
 __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p, int g, int lo, int cut) {
     if (w == W) {
-        tile_part<C, W, W, WJ>(a, p, g, lo, cut);
+        tile_part<C, W, W, WJ, SWAP>(a, p, g, lo, cut);
     } else if constexpr (W + 1 < C::NSPLIT) {
-        tile_dispatch<C, W + 1, WJ>(a, w, p, g, lo, cut);
+        tile_dispatch<C, W + 1, WJ, SWAP>(a, w, p, g, lo, cut);
     }
 }
 
@@ -464,7 +472,8 @@ __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p
 // are adjacent block indices); the common part of the recurrence is
 // recomputed per slice instead of exchanged.
 // WJ: also digest the Coulomb matrix J from the same quartet values.
-template <class C, bool WJ = false>
+// SWAP: C is the exchanged class (see tile_part).
+template <class C, bool WJ = false, bool SWAP = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri(QuartetArgs a) {
     const int lb0 = xcd_block(a.nblk, 8 * C::NSPLIT);
     if (lb0 < 0) return;
@@ -483,7 +492,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     const int cut2 = min(cut, lo2 + a.tq);
     if (cut2 <= lo2) return;
     if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut2 - lo2));
-    tile_dispatch<C, 0, WJ>(a, w, p, g, lo2, cut2);
+    tile_dispatch<C, 0, WJ, SWAP>(a, w, p, g, lo2, cut2);
 }
 
 // FP32 counterpart of tile_part: FP32 records, recurrences and contraction,
