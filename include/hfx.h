@@ -7,7 +7,9 @@
  *     K_ik = sum_jl (ij|kl) P_jl                                   (1)
  *
  * (the exchange matrix of Sec. 2, eq. for V^X, without its -1/2 and without a
- * hybrid mixing fraction, for an open-boundary cluster: no lattice sums).
+ * hybrid mixing fraction, for an open-boundary cluster: no lattice sums);
+ * optionally also the Coulomb matrix J_ij = sum_kl (ij|kl) P_kl from the same
+ * integrals (hfx_build_JK).
  * Two kernels are supported: the bare Coulomb 1/r of the ERI definition in
  * Sec. 2 and the attenuated erfc(omega r)/r of the HSE06 functional named in
  * Sec. 4.  Shells are contracted Gaussians sum_m D_m r^l exp(-alpha_m r^2)
@@ -47,7 +49,7 @@ extern "C" {
 typedef enum {
     HFX_OK = 0,
     HFX_EINVAL = 1,       /* bad size, pointer, exponent, tolerance, omega */
-    HFX_EUNSUPPORTED = 2, /* l > 2, too many primitives */
+    HFX_EUNSUPPORTED = 2, /* l > 2, too many primitives or basis functions */
     HFX_ENOMEM = 3,       /* device allocation or HBM admission failed */
     HFX_EBUSY = 4,        /* server queue full */
     HFX_ENOTFOUND = 5,    /* unknown ticket */

@@ -33,7 +33,6 @@ import math
 import os
 import random
 import sys
-from functools import lru_cache
 
 LMAX = 2
 
@@ -581,18 +580,6 @@ def best_split(la, lb, lc, ld, G):
     recurrence cost is kept; for three or more slices a local search then
     lowers the summed cost of the slices."""
     return [list(p) for p in _best_split(la, lb, lc, ld, G)]
-
-
-def split_f(lc, ld, G):
-    """Partition the ket f components into G groups of consecutive components."""
-    f_list = [f for d in range(lc, lc + ld + 1) for f in cart(d)]
-    n = len(f_list)
-    out = []
-    for g in range(G):
-        lo = (g * n) // G
-        hi = ((g + 1) * n) // G
-        out.append(f_list[lo:hi])
-    return out
 
 
 PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]

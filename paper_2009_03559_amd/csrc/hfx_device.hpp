@@ -234,73 +234,6 @@ __device__ __forceinline__ void prim_quartet32(const PrimRec32 &b, const PrimRec
                          rz * PQx, rz * PQy, rz * PQz, b.i2z, re, k.i2z, rz, 0.5f * ize, acc);
 }
 
-// Digestion of one contracted quartet (AB|CD) with spherical values v[a][b][c][d]:
-//   K'_ac += d v P_bd,  K'_ad += d v P_bc,  K'_bc += d v P_ad,  K'_bd += d v P_ac
-// (four of the eight permutation images; the other four are the transposes,
-// added by K = K' + K'^T).  FP64 atomics into K'.
-template <int NA, int NB, int NC, int ND>
-__device__ __forceinline__ void digest(const double *__restrict__ v, int a0, int b0, int c0, int d0,
-                                       double deg, const double *__restrict__ P, double *K,
-                                       int64_t ld) {
-    double Pbd[NB][ND], Pbc[NB][NC], Pad[NA][ND], Pac[NA][NC];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-#pragma unroll
-        for (int d = 0; d < ND; ++d) Pbd[b][d] = P[(int64_t)(b0 + b) * ld + d0 + d];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) Pbc[b][c] = P[(int64_t)(b0 + b) * ld + c0 + c];
-    }
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-#pragma unroll
-        for (int d = 0; d < ND; ++d) Pad[a][d] = P[(int64_t)(a0 + a) * ld + d0 + d];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) Pac[a][c] = P[(int64_t)(a0 + a) * ld + c0 + c];
-    }
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int d = 0; d < ND; ++d) s = fma(v[((a * NB + b) * NC + c) * ND + d], Pbd[b][d], s);
-            atomicAdd(&K[(int64_t)(a0 + a) * ld + c0 + c], deg * s);
-        }
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) s = fma(v[((a * NB + b) * NC + c) * ND + d], Pbc[b][c], s);
-            atomicAdd(&K[(int64_t)(a0 + a) * ld + d0 + d], deg * s);
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a < NA; ++a)
-#pragma unroll
-                for (int d = 0; d < ND; ++d) s = fma(v[((a * NB + b) * NC + c) * ND + d], Pad[a][d], s);
-            atomicAdd(&K[(int64_t)(b0 + b) * ld + c0 + c], deg * s);
-        }
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a < NA; ++a)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) s = fma(v[((a * NB + b) * NC + c) * ND + d], Pac[a][c], s);
-            atomicAdd(&K[(int64_t)(b0 + b) * ld + d0 + d], deg * s);
-        }
-    }
-}
-
 // Launch parameters of one class pair (bra class cb >= ket class ck).
 struct QuartetArgs {
     const PairHdr *hdr;
