@@ -602,7 +602,7 @@ for _kv in filter(None, os.environ.get("HFX_SPLITS", "").split(",")):
 # (measured the same way).
 DEFAULT_SPLITS_F32 = {
     (2, 1, 1, 1): 1, (2, 1, 2, 0): 1, (2, 2, 1, 0): 1, (2, 2, 2, 0): 1,
-    (2, 1, 2, 1): 2, (2, 2, 1, 1): 2, (2, 2, 2, 1): 3, (2, 2, 2, 2): 6,
+    (2, 1, 2, 1): 2, (2, 2, 1, 1): 1, (2, 2, 2, 1): 2, (2, 2, 2, 2): 5,
 }
 for _kv in filter(None, os.environ.get("HFX_SPLITS_F32", "").split(",")):
     _k, _v = _kv.split(":")
@@ -641,8 +641,9 @@ def write_jk_tu(outdir, tag, suffix, nm, kernel, launcher, swap="false"):
 # (for these classes the recurrence shared between slices is smaller that way),
 # with the slice counts of the exchanged class.  The digestion images are then
 # the transposes of the usual ones, which K = K' + K'^T absorbs.  FP64 direct
-# launches only.  Measured on the 256-atom shard: (dp|pp) -8 %, (dd|pp) -7 %,
-# (dd|ds) -4 %; (dd|dp) exchanged spills to scratch and stays as it is.
+# and persistent launches.  Measured on the 256-atom shard: (dp|pp) -8 %,
+# (dd|pp) -7 %, (dd|ds) -4 %; (dd|dp) exchanged spills to scratch and stays
+# as it is.
 # HFX_TRANSPOSED="2111:2,2211:3" overrides (tuning); "none" turns it off.
 TRANSPOSED = {(2, 1, 1, 1): 2, (2, 2, 1, 1): 3, (2, 2, 2, 0): 2}
 _tr = os.environ.get("HFX_TRANSPOSED", "")
@@ -793,9 +794,9 @@ def generate(outdir, T="double", splits=None):
             "}",
             f"void launch_persist_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
             "                        unsigned grid, hipStream_t s) {",
-            f"  hipLaunchKernelGGL(k_eri_persist<{nm}>, dim3(grid), dim3(64), 0, s, j, nj, vt, h, claim);",
+            f"  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri_persist<{dn}, {sw}>), dim3(grid), dim3(64), 0, s, j, nj, vt, h, claim);",
             "}",
-            f"int nsplit_{tag}() {{ return {nm}::NSPLIT; }}",
+            f"int nsplit_{tag}() {{ return {dn}::NSPLIT; }}",
             f"void launch_eval_{tag}(const PairHdr *h, const PrimRec *p, const int32_t *bk, int n, int op,",
             "                    double om2, const double *tab, double *out, hipStream_t s) {",
             f"  hipLaunchKernelGGL(k_eval<{nm}>, dim3((n + 63) / 64), dim3(64), 0, s, h, p, bk, n, op, om2, tab, out);",

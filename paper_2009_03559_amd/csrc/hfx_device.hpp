@@ -524,7 +524,7 @@ struct BatchJob {
     int tq;
 };
 
-template <class C, bool F32>
+template <class C, bool F32, bool SWAP = false>
 __device__ __forceinline__ void persist_loop(const BatchJob *__restrict__ jobs, int njobs, long long vtotal,
                                              unsigned long long *head, int claim) {
     for (;;) {
@@ -555,15 +555,15 @@ __device__ __forceinline__ void persist_loop(const BatchJob *__restrict__ jobs, 
             if (cut2 <= lo2) continue;
             if (w == 0 && threadIdx.x == 0 && J.a.count) atomicAdd(&J.a.count[0], (unsigned long long)(cut2 - lo2));
             if constexpr (F32) tile_dispatch32<C, 0>(J.a, w, p, g, lo2, cut2);
-            else tile_dispatch<C, 0>(J.a, w, p, g, lo2, cut2);
+            else tile_dispatch<C, 0, false, SWAP>(J.a, w, p, g, lo2, cut2);
         }
     }
 }
 
-template <class C>
+template <class C, bool SWAP = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri_persist(
     const BatchJob *__restrict__ jobs, int njobs, long long vtotal, unsigned long long *head, int claim) {
-    persist_loop<C, false>(jobs, njobs, vtotal, head, claim);
+    persist_loop<C, false, SWAP>(jobs, njobs, vtotal, head, claim);
 }
 
 template <class C>
