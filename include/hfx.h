@@ -189,7 +189,10 @@ hfx_status hfx_build_K_batch(int32_t nsys, const hfx_pairs *p, const double *con
 /* Serving: a request loop that admits K-builds against an HBM budget
  * (bytes of device memory the server may hold for queued work) and runs
  * at most max_inflight of them concurrently on its own streams, so work of
- * requests that arrive while others run overlaps on the device. */
+ * requests that arrive while others run overlaps on the device.  At most
+ * 4096 requests wait at a time (the environment variable HFX_SERVER_QUEUE,
+ * read here, sets another capacity).  Errors: EINVAL (budget <= 0,
+ * max_inflight not in [1, 64]), EDEVICE. */
 hfx_status hfx_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, hfx_server *s);
 
 /* Queue one K-build (non-blocking).  P_dev/K_dev must stay valid until the
@@ -211,9 +214,12 @@ int64_t hfx_pairs_npair(hfx_pairs p);
 /* Device bytes held by a pair handle. */
 int64_t hfx_pairs_device_bytes(hfx_pairs p);
 
-/* Raw spherical integrals of listed shell quartets, computed by the same
- * class kernels as hfx_build_K (used to check sampled outputs of large
- * builds).  quartets: host, 4*n shell indices (I,J,K,L) in any order.
+/* Raw spherical integrals of listed shell quartets (used to check sampled
+ * outputs of large builds) evaluated with the code of the FP64 exchange
+ * build: its per-slice vertical recurrences, its exchanged class layouts and
+ * its horizontal recurrence and spherical transform, one quartet per lane,
+ * every primitive quartet included (no screening, no digestion).
+ * quartets: host, 4*n shell indices (I,J,K,L) in any order.
  * out: host, receives for each quartet its (2lI+1)(2lJ+1)(2lK+1)(2lL+1)
  * values in [i][j][k][l] order, packed one after another.  Synchronises.
  * Errors: EINVAL, EDEVICE. */

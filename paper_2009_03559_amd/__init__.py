@@ -30,8 +30,8 @@ EXPORTS = ["hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_bu
            "hfx_build_K_shard",
            "hfx_build_K_batch",
            "hfx_server_create", "hfx_submit", "hfx_poll", "hfx_pairs_nbf", "hfx_pairs_npair",
-           "hfx_pairs_device_bytes", "hfx_eval_quartets", "hfx_pairs_destroy", "hfx_server_destroy",
-           "hfx_last_error"]
+           "hfx_pairs_device_bytes", "hfx_eval_quartets", "hfx_pairs_destroy",
+           "hfx_server_destroy", "hfx_last_error"]
 
 
 class HfxError(RuntimeError):

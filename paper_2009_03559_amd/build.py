@@ -25,6 +25,25 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-munsafe-fp-ato
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-I" + GEN]
 
 
+COMMON_HEADERS = [os.path.join(CSRC, "hfx_device.hpp"), os.path.join(CSRC, "hfx_internal.hpp"),
+                  os.path.join(ROOT, "include", "hfx.h")]
+
+
+def _header_of(src: str) -> str:
+    return src.replace("tu_", "eri_").replace("_jk.hip", ".hip").replace(".hip", ".h")
+
+
+def _stale(src: str) -> bool:
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + COMMON_HEADERS
+    h = _header_of(src)
+    if os.path.exists(h):
+        deps.append(h)
+    return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
     cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
@@ -34,8 +53,10 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
-    """Generate, compile and link; returns the library path."""
+def build(jobs: int | None = None, verbose: bool = True, only_changed: bool = False) -> str:
+    """Generate, compile and link; returns the library path.  only_changed:
+    recompile only translation units older than their sources (development
+    builds); the default compiles everything."""
     os.makedirs(GEN, exist_ok=True)
     os.makedirs(OBJ, exist_ok=True)
     subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_eri.py"), "--outdir", GEN,
@@ -44,17 +65,14 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     srcs += [os.path.join(CSRC, f) for f in ("hfx_host.hip", "hfx_serve.hip")]
     # largest classes first so the pool finishes together (a class's
     # Coulomb-digesting variant shares its header)
-    def header(src):
-        return src.replace("tu_", "eri_").replace("_jk.hip", ".hip").replace(".hip", ".h")
-
-    srcs.sort(key=lambda s: -os.path.getsize(header(s)) if os.path.exists(header(s)) else 0)
+    srcs.sort(key=lambda s: -os.path.getsize(_header_of(s)) if os.path.exists(_header_of(s)) else 0)
+    todo = [s for s in srcs if _stale(s)] if only_changed else srcs
     jobs = jobs or min(16, os.cpu_count() or 4)
-    objs = []
     with cf.ThreadPoolExecutor(jobs) as ex:
-        for o in ex.map(_compile, srcs):
-            objs.append(o)
+        for o in ex.map(_compile, todo):
             if verbose:
                 print("compiled", os.path.basename(o), flush=True)
+    objs = [os.path.join(OBJ, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)
@@ -62,4 +80,4 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(only_changed="--changed" in sys.argv)

@@ -356,7 +356,11 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
     share of every spherical value, which is digested at once:
       K'_ac += d v P_bd, K'_ad += d v P_bc, K'_bc += d v P_ad, K'_bd += d v P_ac.
     Shares of all slices add up in K' through the atomics."""
-    T = em.T
+    # the contracted array may be FP32 (mixed mode); the horizontal
+    # recurrence, spherical transform and digestion always run in FP64 (once
+    # per contracted quartet, a small share of the work)
+    T = "double"
+    AT = em.T
     E, F = la + lb, lc + ld
     e_list = [e for d in range(la, E + 1) for e in cart(d)]
     eidx = {e: k for k, e in enumerate(e_list)}
@@ -365,9 +369,17 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
     nas, nbs, ncs, nds = 2 * la + 1, 2 * lb + 1, 2 * lc + 1, 2 * ld + 1
     ax = "xyz"
     L = em.lines
-    L.append(f"  __device__ __forceinline__ static void {name}(const {T}* __restrict__ acc,")
-    L.append(f"      {T} ABx, {T} ABy, {T} ABz, {T} CDx, {T} CDy, {T} CDz, int a0, int b0, int c0, int d0,")
-    L.append(f"      double deg, const double* __restrict__ P, double* K, int64_t ld) {{")
+    L.append(f"  __device__ __forceinline__ static void {name}(const {AT}* __restrict__ acc,")
+    if mode == "E":
+        # raw values: this slice's share of every spherical value is added to
+        # out[(as nbs + bs) sab + (cs nds + ds) scd] (the caller's lane-private
+        # output, strides chosen by the caller so exchanged classes land in the
+        # original index order)
+        L.append(f"      {T} ABx, {T} ABy, {T} ABz, {T} CDx, {T} CDy, {T} CDz, int64_t sab, int64_t scd,")
+        L.append("      double* __restrict__ out) {")
+    else:
+        L.append(f"      {T} ABx, {T} ABy, {T} ABz, {T} CDx, {T} CDy, {T} CDz, int a0, int b0, int c0, int d0,")
+        L.append(f"      double deg, const double* __restrict__ P, double* K, int64_t ld) {{")
     brec, border = hrr_plan(la, lb)
     krec, korder = hrr_plan(lc, ld)
     jtouched = set()
@@ -397,7 +409,7 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
                     for b, cb in SPH[lb][bs].items():
                         c = ca * cb
                         nm = names[(a, b)]
-                        terms.append(nm if c == 1.0 else f"{em.lit(c)} * {nm}")
+                        terms.append(nm if c == 1.0 else f"{fmt(c)} * {nm}")
                 L.append(f"    const {T} s{as_}_{bs}_{jf} = " + " + ".join(terms) + ";")
     # ket HRR + spherical with the missing f as structural zeros, then digestion
     if mode == "K":
@@ -407,14 +419,14 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
                 for x in range(n):
                     L.append(f"    double kb{ks}{bs}_{x} = 0.0;")
     for as_ in range(nas):
-        if mode == "D":
+        if mode in ("D", "E"):
             L.append("    {")
         else:
             L.append(f"    {{ const double* Pa = P + (int64_t)(a0 + {as_}) * ld;")
         if mode == "K":
             L.append("      double kac[%d] = {0}; double kad[%d] = {0};" % (ncs, nds))
         for bs in range(nbs):
-            if mode == "D":
+            if mode in ("D", "E"):
                 L.append("      {")
             else:
                 L.append(f"      {{ const double* Pb = P + (int64_t)(b0 + {bs}) * ld;")
@@ -447,7 +459,7 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
                             nm = names[(c_, d_)]
                             if nm is None:
                                 continue
-                            terms.append(nm if c == 1.0 else f"{em.lit(c)} * {nm}")
+                            terms.append(nm if c == 1.0 else f"{fmt(c)} * {nm}")
                     if terms:
                         v = f"v{as_}_{bs}_{cs}_{ds}"
                         L.append(f"        const double {v} = " + " + ".join(terms) + ";")
@@ -456,6 +468,11 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
                 # Schwarz diagonal (ab|ab): K is the diagonal accumulator here
                 if (as_, bs) in vals:
                     L.append(f"        K[{as_ * nbs + bs}] += {vals[(as_, bs)]};")
+                L.append("      }")
+                continue
+            if mode == "E":
+                for (cs, ds) in sorted(vals):
+                    L.append(f"        out[{as_ * nbs + bs} * sab + {cs * nds + ds} * scd] += {vals[(cs, ds)]};")
                 L.append("      }")
                 continue
             if mode == "J":
@@ -482,14 +499,14 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
                     L.append(f"        kad[{ds}] += " + " + ".join(t1) + ";")
                     L.append(f"        kbd{bs}_{ds} += " + " + ".join(t2) + ";")
             L.append("      }")
-        if mode in ("J", "D"):
+        if mode in ("J", "D", "E"):
             L.append("    }")
             continue
         L.append(f"      double* Ka = K + (int64_t)(a0 + {as_}) * ld;")
         L.append(f"      for (int x = 0; x < {ncs}; ++x) atomicAdd(&Ka[c0 + x], deg * kac[x]);")
         L.append(f"      for (int x = 0; x < {nds}; ++x) atomicAdd(&Ka[d0 + x], deg * kad[x]);")
         L.append("    }")
-    if mode == "D":
+    if mode in ("D", "E"):
         L.append("  }")
         return
     if mode == "J":
@@ -632,8 +649,7 @@ def write_jk_tu(outdir, tag, suffix, nm, kernel, launcher, swap="false"):
         "}",
         "}  // namespace hfx",
     ]
-    with open(os.path.join(outdir, f"tu_{tag}{suffix}_jk.hip"), "w") as f:
-        f.write("\n".join(tu) + "\n")
+    write_if_changed(os.path.join(outdir, f"tu_{tag}{suffix}_jk.hip"), "\n".join(tu) + "\n")
 
 
 # Classes evaluated with the roles of the pairs exchanged, (cd|ab) in place of
@@ -657,6 +673,19 @@ if _tr != "none":
 
 def class_tag(c):
     return "".join(str(x) for x in c)
+
+
+def write_if_changed(path, text):
+    """Write only when the content differs, so unchanged outputs keep their
+    time stamps (incremental builds recompile only what changed)."""
+    try:
+        with open(path) as f:
+            if f.read() == text:
+                return
+    except OSError:
+        pass
+    with open(path, "w") as f:
+        f.write(text)
 
 
 def emit_struct(em, la, lb, lc, ld, nm, G):
@@ -684,8 +713,21 @@ def emit_struct(em, la, lb, lc, ld, nm, G):
         split_cost.append(c)
         emit_digest_part(em, la, lb, lc, ld, f"dig_p{g}", ft)
         emit_digest_part(em, la, lb, lc, ld, f"digJ_p{g}", ft, mode="J")
+        if em.T == "double":
+            emit_digest_part(em, la, lb, lc, ld, f"store_p{g}", ft, mode="E")
         if (la, lb) == (lc, ld):
             emit_digest_part(em, la, lb, lc, ld, f"diag_p{g}", ft, mode="D")
+            # largest diagonal value [e0|e0] of the contracted array (bra and
+            # ket are the same pair): the scale of the horizontal
+            # recurrence's inputs
+            e_all = [e for d in range(la, la + lb + 1) for e in cart(d)]
+            ei = {e: k for k, e in enumerate(e_all)}
+            fi = {f: k for k, f in enumerate(ft)}
+            em.lines.append(f"  __device__ __forceinline__ static void diagE_p{g}(const {em.T}* __restrict__ acc, "
+                            "double* __restrict__ m) {")
+            for f in ft:
+                em.lines.append(f"    m[0] = fmax(m[0], (double)acc[{ei[f] * len(ft) + fi[f]}]);")
+            em.lines.append("  }")
     em.lines.append(f"  static constexpr int NACCP[{G}] = {{{', '.join(str(x) for x in nacc_p)}}};")
     T_ = em.T
     em.lines.append("  template <int W> __device__ __forceinline__ static void vrr_p(const %s* __restrict__ g," % T_)
@@ -698,7 +740,7 @@ def emit_struct(em, la, lb, lc, ld, nm, G):
                         " WQx, WQy, WQz, i2z, roz, i2e, roe, i2ze, acc);")
     em.lines.append("  }")
     em.lines.append("  template <int W> __device__ __forceinline__ static void dig(const %s* __restrict__ acc," % T_)
-    em.lines.append("      %s ABx, %s ABy, %s ABz, %s CDx, %s CDy, %s CDz, int a0, int b0, int c0, int d0," % ((T_,) * 6))
+    em.lines.append("      double ABx, double ABy, double ABz, double CDx, double CDy, double CDz, int a0, int b0, int c0, int d0,")
     em.lines.append("      double deg, const double* __restrict__ P, double* K, int64_t ld) {")
     for g_ in range(G):
         kw = "if" if g_ == 0 else "else if"
@@ -708,14 +750,29 @@ def emit_struct(em, la, lb, lc, ld, nm, G):
     if (la, lb) == (lc, ld):
         # share of slice W in the diagonal values (ab|ab), for the Schwarz factors
         em.lines.append("  template <int W> __device__ __forceinline__ static void diag(const %s* __restrict__ acc," % T_)
-        em.lines.append("      %s ABx, %s ABy, %s ABz, double* __restrict__ d) {" % ((T_,) * 3))
+        em.lines.append("      double ABx, double ABy, double ABz, double* __restrict__ d) {")
         for g_ in range(G):
             kw = "if" if g_ == 0 else "else if"
             em.lines.append(f"    {kw} constexpr (W == {g_}) diag_p{g_}(acc, ABx, ABy, ABz, ABx, ABy, ABz, 0, 0, 0, 0,"
                             " 1.0, nullptr, d, 0);")
         em.lines.append("  }")
+        em.lines.append("  template <int W> __device__ __forceinline__ static void diagE(const %s* __restrict__ acc,"
+                        " double* __restrict__ m) {" % T_)
+        for g_ in range(G):
+            kw = "if" if g_ == 0 else "else if"
+            em.lines.append(f"    {kw} constexpr (W == {g_}) diagE_p{g_}(acc, m);")
+        em.lines.append("  }")
+    if T_ == "double":
+        # this slice's share of the raw spherical values (hfx_eval_quartets)
+        em.lines.append("  template <int W> __device__ __forceinline__ static void store(const %s* __restrict__ acc," % T_)
+        em.lines.append("      double ABx, double ABy, double ABz, double CDx, double CDy, double CDz, int64_t sab,")
+        em.lines.append("      int64_t scd, double* __restrict__ out) {")
+        for g_ in range(G):
+            kw = "if" if g_ == 0 else "else if"
+            em.lines.append(f"    {kw} constexpr (W == {g_}) store_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, sab, scd, out);")
+        em.lines.append("  }")
     em.lines.append("  template <int W> __device__ __forceinline__ static void digJ(const %s* __restrict__ acc," % T_)
-    em.lines.append("      %s ABx, %s ABy, %s ABz, %s CDx, %s CDy, %s CDz, int a0, int b0, int c0, int d0," % ((T_,) * 6))
+    em.lines.append("      double ABx, double ABy, double ABz, double CDx, double CDy, double CDz, int a0, int b0, int c0, int d0,")
     em.lines.append("      double deg, const double* __restrict__ P, double* J, int64_t ld) {")
     for g_ in range(G):
         kw = "if" if g_ == 0 else "else if"
@@ -750,8 +807,7 @@ def generate(outdir, T="double", splits=None):
             # the same integrals with the pairs' roles exchanged, sliced over
             # the components of the original bra pair (see TRANSPOSED)
             emit_struct(em, lc, ld, la, lb, nm + "T", TRANSPOSED[(la, lb, lc, ld)])
-        with open(os.path.join(outdir, f"eri_{tag}{suffix}.h"), "w") as f:
-            f.write("\n".join(em.lines) + "\n")
+        write_if_changed(os.path.join(outdir, f"eri_{tag}{suffix}.h"), "\n".join(em.lines) + "\n")
         model[tag] = dict(vrr_flops=vflops, post_flops=pflops, nacc=NE * NF,
                           nout=nsph, split=G, split_vrr_flops=split_cost)
         diag = (la, lb) == (lc, ld)
@@ -774,8 +830,7 @@ def generate(outdir, T="double", splits=None):
                 f"int nsplit32_{tag}() {{ return {nm}::NSPLIT; }}",
             ]
             tu.append("}  // namespace hfx")
-            with open(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "w") as f:
-                f.write("\n".join(tu) + "\n")
+            write_if_changed(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "\n".join(tu) + "\n")
             write_jk_tu(outdir, tag, suffix, nm, "k_eri32", "launch_erijk32")
             continue
         # direct launches of a class in TRANSPOSED use the exchanged struct
@@ -799,14 +854,15 @@ def generate(outdir, T="double", splits=None):
             f"int nsplit_{tag}() {{ return {dn}::NSPLIT; }}",
             f"void launch_eval_{tag}(const PairHdr *h, const PrimRec *p, const int32_t *bk, int n, int op,",
             "                    double om2, const double *tab, double *out, hipStream_t s) {",
-            f"  hipLaunchKernelGGL(k_eval<{nm}>, dim3((n + 63) / 64), dim3(64), 0, s, h, p, bk, n, op, om2, tab, out);",
+            f"  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eval<{dn}, {sw}>), dim3((n + 63) / 64), dim3(64), 0, s, h, p, bk, n, op,",
+            "                     om2, tab, out);",
             "}",
         ]
         if diag:
             tu += [
                 f"void launch_schwarz_{class_tag((la, lb))}(const PairHdr *h, const PrimRec *p, const int32_t *ids, int n,",
-                "                    int op, double om2, const double *tab, double *Q, hipStream_t s) {",
-                f"  hipLaunchKernelGGL(k_schwarz<{nm}>, dim3((n + 63) / 64), dim3(64), 0, s, h, p, ids, n, op, om2, tab, Q);",
+                "                    int op, double om2, const double *tab, double *Q, double *E, hipStream_t s) {",
+                f"  hipLaunchKernelGGL(k_schwarz<{nm}>, dim3((n + 63) / 64), dim3(64), 0, s, h, p, ids, n, op, om2, tab, Q, E);",
                 "}",
                 f"void launch_primbound_{class_tag((la, lb))}(const PairHdr *h, PrimRec *p, const int32_t *ids, int n,",
                 "                    int op, double om2, const double *tab, hipStream_t s) {",
@@ -814,8 +870,7 @@ def generate(outdir, T="double", splits=None):
                 "}",
             ]
         tu.append("}  // namespace hfx")
-        with open(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "w") as f:
-            f.write("\n".join(tu) + "\n")
+        write_if_changed(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "\n".join(tu) + "\n")
         write_jk_tu(outdir, tag, suffix, dn, "k_eri", "launch_erijk", sw)
     return model
 
@@ -843,8 +898,7 @@ def write_model(outdir, model):
         "}",
         "}  // namespace hfx",
     ]
-    with open(os.path.join(outdir, "model.hip"), "w") as f:
-        f.write("\n".join(src) + "\n")
+    write_if_changed(os.path.join(outdir, "model.hip"), "\n".join(src) + "\n")
 
 
 def main():

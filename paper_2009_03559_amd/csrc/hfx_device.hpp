@@ -36,8 +36,12 @@ struct PrimRec {
 };
 
 // FP32 copy of a record, used for quartets evaluated in FP32 (mixed mode).
+// The product centre P stays FP64: P - Q is formed in FP64 and then rounded,
+// so its error is relative to |P - Q|, not to the distance of P from the
+// coordinate origin.
 struct PrimRec32 {
-    float z, i2z, Px, Py, Pz, PAx, PAy, PAz, K, B;
+    double Px, Py, Pz;
+    float z, i2z, PAx, PAy, PAz, K, B, pad;
 };
 
 // Read-only views in the constant address space (scalar loads when uniform).
@@ -52,8 +56,8 @@ __device__ __forceinline__ PrimRec load_rec(CPrimRec *r) {
 }
 __device__ __forceinline__ PrimRec32 load_rec(CPrimRec32 *r) {
     PrimRec32 x;
-    x.z = r->z; x.i2z = r->i2z; x.Px = r->Px; x.Py = r->Py; x.Pz = r->Pz;
-    x.PAx = r->PAx; x.PAy = r->PAy; x.PAz = r->PAz; x.K = r->K; x.B = r->B;
+    x.Px = r->Px; x.Py = r->Py; x.Pz = r->Pz; x.z = r->z; x.i2z = r->i2z;
+    x.PAx = r->PAx; x.PAy = r->PAy; x.PAz = r->PAz; x.K = r->K; x.B = r->B; x.pad = 0.0f;
     return x;
 }
 
@@ -209,7 +213,7 @@ __device__ __forceinline__ void prim_quartet32(const PrimRec32 &b, const PrimRec
     const float rs = rsqrtf(ze);
     const float ize = rs * rs;
     const float rho = b.z * k.z * ize;
-    const float PQx = b.Px - k.Px, PQy = b.Py - k.Py, PQz = b.Pz - k.Pz;
+    const float PQx = (float)(b.Px - k.Px), PQy = (float)(b.Py - k.Py), PQz = (float)(b.Pz - k.Pz);
     const float T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
     const float pref = b.K * k.K * rs;
     float g[C::L + 1];
@@ -257,6 +261,15 @@ struct QuartetArgs {
     int32_t same;             // bra class == ket class: quartet (p,q) needs q <= p
     double tau;               // ket range: tau <= Q_p Q_q < tau_hi
     double tau_hi;
+    // Mixed precision: the quartets of a block split at Q_p Q_q = cut /
+    // (A_p A_g), A = E / Q the ratio of a pair's FP32 error scale to its
+    // Schwarz factor (A_g: the largest of ket group g), i.e. FP32 where the
+    // estimated FP32 error E_p E_q is below the cut.  part 0: no split;
+    // 1: the FP64 side; 2: the FP32 side.
+    int32_t part;
+    double mixed_cut;
+    const double *bra_A;      // per bra slot
+    const double *ket_gA;     // per ket group
     int32_t op;
     double om2;               // omega^2
     double prim_tau;          // primitive quartets with B_ab B_cd < prim_tau may be skipped
@@ -321,9 +334,15 @@ __device__ __forceinline__ int ket_cut(const QuartetArgs &a, int p, int g, int *
         if (g > gp) return lo;  // empty: every slot of group g is after p
         if (g == gp) hi = p + 1;
     }
-    lo = first_below(a.ket_Q, lo, hi, Qp, a.tau_hi);
+    double tlo = a.tau, thi = a.tau_hi;
+    if (a.part) {
+        const double ts = a.mixed_cut / (a.bra_A[p] * a.ket_gA[g]);
+        if (a.part == 1) tlo = fmax(tlo, ts);
+        else thi = ts;  // ts <= tau: empty
+    }
+    lo = first_below(a.ket_Q, lo, hi, Qp, thi);
     *lo_out = lo;
-    return first_below(a.ket_Q, lo, hi, Qp, a.tau);
+    return first_below(a.ket_Q, lo, hi, Qp, tlo);
 }
 
 // One wave's work on one tile: 64 lanes walk the screened ket range of bra
@@ -467,12 +486,12 @@ __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, 
             if (bh.diag) deg *= 0.5;
             if (kh.diag) deg *= 0.5;
             if (bh.id == kh.id) deg *= 0.5;
-            C::template dig<W>(acc, (float)bh.ABx, (float)bh.ABy, (float)bh.ABz, (float)kh.ABx, (float)kh.ABy,
-                               (float)kh.ABz, bh.bfA, bh.bfB, kh.bfA, kh.bfB, deg, a.P, a.K, a.ld);
+            // horizontal recurrence, spherical transform and digestion in FP64
+            C::template dig<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB, kh.bfA,
+                               kh.bfB, deg, a.P, a.K, a.ld);
             if constexpr (WJ)
-                C::template digJ<W>(acc, (float)bh.ABx, (float)bh.ABy, (float)bh.ABz, (float)kh.ABx,
-                                    (float)kh.ABy, (float)kh.ABz, bh.bfA, bh.bfB, kh.bfA, kh.bfB, deg, a.P, a.J,
-                                    a.ld);
+                C::template digJ<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB, kh.bfA,
+                                    kh.bfB, deg, a.P, a.J, a.ld);
         }
     }
     if (W == 0 && a.count && nprim) atomicAdd(&a.count[1], nprim);
@@ -578,7 +597,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
 template <class C, int W>
 __device__ __forceinline__ void schwarz_slices(const PairHdr &h, const PrimRec *__restrict__ prim, int op,
                                                double om2, const double *__restrict__ tab, double om,
-                                               double *diag) {
+                                               double *diag, double *emax) {
     double acc[C::NACCP[W]];
 #pragma unroll
     for (int i = 0; i < C::NACCP[W]; ++i) acc[i] = 0.0;
@@ -590,17 +609,28 @@ __device__ __forceinline__ void schwarz_slices(const PairHdr &h, const PrimRec *
         }
     }
     C::template diag<W>(acc, h.ABx, h.ABy, h.ABz, diag);
-    if constexpr (W + 1 < C::NSPLIT) schwarz_slices<C, W + 1>(h, prim, op, om2, tab, om, diag);
+    C::template diagE<W>(acc, emax);
+    if constexpr (W + 1 < C::NSPLIT) schwarz_slices<C, W + 1>(h, prim, op, om2, tab, om, diag, emax);
 }
 
 // Schwarz factor of each pair of a pair class: Q = sqrt(max_ab (ab|ab)), the
-// diagonal class (IJ|IJ) evaluated slice by slice.
+// diagonal class (IJ|IJ) evaluated slice by slice.  Also the scale of the
+// integrals' rounding error in FP32:
+//     E = s_la s_lb (1 + max_i |AB_i|)^lb sqrt(max_e [e0|e0]),
+// where [e0|e0] (|e| = la .. la+lb) are the diagonal contracted inputs of the
+// horizontal recurrence (so |[e0|f0]| <= sqrt([e0|e0] [f0|f0]) by Schwarz),
+// (1 + |AB|)^lb bounds the sum of the absolute coefficients with which the
+// recurrence combines them and s_l (1 for s and p, 2 for d) that of a
+// spherical row.  Every value of a quartet is then at most E_IJ E_KL in size
+// (so E >= Q), and rounding errors of its inputs reach it multiplied by at
+// most those sums: evaluated in FP32 a quartet is in error by about
+// eps32 E_IJ E_KL, however small its value and its bound Q_IJ Q_KL are.
 template <class C>
 __global__ __launch_bounds__(64) void k_schwarz(const PairHdr *__restrict__ hdr,
                                                 const PrimRec *__restrict__ prim,
                                                 const int32_t *__restrict__ ids, int n, int op,
                                                 double om2, const double *__restrict__ tab,
-                                                double *__restrict__ Q) {
+                                                double *__restrict__ Q, double *__restrict__ E) {
     const int t = blockIdx.x * 64 + threadIdx.x;
     if (t >= n) return;
     const PairHdr h = hdr[ids[t]];
@@ -609,11 +639,17 @@ __global__ __launch_bounds__(64) void k_schwarz(const PairHdr *__restrict__ hdr,
     double diag[NA * NB];
 #pragma unroll
     for (int i = 0; i < NA * NB; ++i) diag[i] = 0.0;
-    schwarz_slices<C, 0>(h, prim, op, om2, tab, om, diag);
+    double emax = 0.0;
+    schwarz_slices<C, 0>(h, prim, op, om2, tab, om, diag, &emax);
     double mx = 0.0;
 #pragma unroll
     for (int i = 0; i < NA * NB; ++i) mx = fmax(mx, diag[i]);
     Q[h.id] = sqrt(mx);
+    const double ab = 1.0 + fmax(fabs(h.ABx), fmax(fabs(h.ABy), fabs(h.ABz)));
+    double amp = (C::LA == 2 ? 2.0 : 1.0) * (C::LB == 2 ? 2.0 : 1.0);
+#pragma unroll
+    for (int k = 0; k < C::LB; ++k) amp *= ab;
+    E[h.id] = amp * sqrt(emax);
 }
 
 // Schwarz factor B of every primitive pair of the pairs of one pair class
@@ -654,30 +690,50 @@ __global__ __launch_bounds__(64) void k_primbound(const PairHdr *__restrict__ hd
     }
 }
 
-// Raw integrals of listed quartets (canonical pair ids bra, ket), one per lane.
-template <class C>
-__global__ __launch_bounds__(64) void k_eval(const PairHdr *__restrict__ hdr,
-                                             const PrimRec *__restrict__ prim,
+// Raw integrals of listed quartets, one per lane, with the code of the
+// exchange build: the per-slice recurrences, the exchanged class structs and
+// the same horizontal recurrence and spherical transform; every primitive
+// quartet is evaluated (no screening).  Each slice adds its share of every
+// spherical value to the lane's output block.
+// x: the pair whose records enter the recurrence as its bra, y: as its ket.
+template <class C, int W>
+__device__ __forceinline__ void eval_slices(const PairHdr &x, const PairHdr &y, const PrimRec *__restrict__ prim,
+                                            int op, double om2, const double *__restrict__ tab, double om,
+                                            int64_t sab, int64_t scd, double *out) {
+    double acc[C::NACCP[W]];
+#pragma unroll
+    for (int i = 0; i < C::NACCP[W]; ++i) acc[i] = 0.0;
+    for (int kp = 0; kp < y.n; ++kp) {
+        const PrimRec k = prim[y.off + kp];
+        for (int bp = 0; bp < x.n; ++bp) {
+            const PrimRec b = prim[x.off + bp];
+            prim_quartet_p<C, W>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc, om);
+        }
+    }
+    C::template store<W>(acc, x.ABx, x.ABy, x.ABz, y.ABx, y.ABy, y.ABz, sab, scd, out);
+    if constexpr (W + 1 < C::NSPLIT) eval_slices<C, W + 1>(x, y, prim, op, om2, tab, om, sab, scd, out);
+}
+
+// bk: canonical pair ids (bra of the class's higher pair class, ket); out:
+// NOUT values per quartet in [a][b][c][d] order of the canonical bra and ket.
+// SWAP: C is the exchanged struct (cd|ab); its output index order is then
+// the transpose, undone by the strides.
+template <class C, bool SWAP = false>
+__global__ __launch_bounds__(64) void k_eval(const PairHdr *__restrict__ hdr, const PrimRec *__restrict__ prim,
                                              const int32_t *__restrict__ bk, int n, int op, double om2,
                                              const double *__restrict__ tab, double *__restrict__ out) {
     const int t = blockIdx.x * 64 + threadIdx.x;
     if (t >= n) return;
     const PairHdr bh = hdr[bk[2 * t]], kh = hdr[bk[2 * t + 1]];
     const double om = sqrt(om2);
-    double acc[C::NACC];
-#pragma unroll
-    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.0;
-    for (int kp = 0; kp < kh.n; ++kp) {
-        const PrimRec k = prim[kh.off + kp];
-        for (int bp = 0; bp < bh.n; ++bp) {
-            const PrimRec b = prim[bh.off + bp];
-            prim_quartet<C>(b, k.z, k.i2z, k.Px, k.Py, k.Pz, k.PAx, k.PAy, k.PAz, k.K, op, om2, tab, acc, om);
-        }
-    }
-    double v[C::NOUT];
-    C::post(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, v);
-#pragma unroll
-    for (int i = 0; i < C::NOUT; ++i) out[(int64_t)t * C::NOUT + i] = v[i];
+    double *o = out + (int64_t)t * C::NOUT;
+    for (int i = 0; i < C::NOUT; ++i) o[i] = 0.0;
+    // struct's (ab) block index runs over its own bra pair, (cd) over its ket
+    constexpr int64_t nab = (2 * C::LA + 1) * (2 * C::LB + 1), ncd = (2 * C::LC + 1) * (2 * C::LD + 1);
+    if constexpr (SWAP)
+        eval_slices<C, 0>(kh, bh, prim, op, om2, tab, om, 1, nab, o);
+    else
+        eval_slices<C, 0>(bh, kh, prim, op, om2, tab, om, ncd, 1, o);
 }
 
 }  // namespace hfx

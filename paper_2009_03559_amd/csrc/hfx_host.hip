@@ -146,16 +146,17 @@ __global__ void k_to_f32(const PrimRec *__restrict__ in, int64_t n, PrimRec32 *_
     if (t >= n) return;
     const PrimRec r = in[t];
     PrimRec32 o;
+    o.Px = r.Px;
+    o.Py = r.Py;
+    o.Pz = r.Pz;
     o.z = (float)r.z;
     o.i2z = (float)r.i2z;
-    o.Px = (float)r.Px;
-    o.Py = (float)r.Py;
-    o.Pz = (float)r.Pz;
     o.PAx = (float)r.PAx;
     o.PAy = (float)r.PAy;
     o.PAz = (float)r.PAz;
     o.K = (float)r.K;
     o.B = (float)r.B;
+    o.pad = 0.0f;
     out[t] = o;
 }
 
@@ -238,12 +239,12 @@ HFX_FOR_CLASSES(DECL)
     void launch_erijk32_##T(const QuartetArgs &, unsigned, hipStream_t);
 HFX_FOR_CLASSES(DECL32)
 #undef DECL32
-void launch_schwarz_00(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
-void launch_schwarz_10(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
-void launch_schwarz_11(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
-void launch_schwarz_20(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
-void launch_schwarz_21(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
-void launch_schwarz_22(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, hipStream_t);
+void launch_schwarz_00(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, double *, hipStream_t);
+void launch_schwarz_10(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, double *, hipStream_t);
+void launch_schwarz_11(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, double *, hipStream_t);
+void launch_schwarz_20(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, double *, hipStream_t);
+void launch_schwarz_21(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, double *, hipStream_t);
+void launch_schwarz_22(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *, double *, double *, hipStream_t);
 #define PB(T) void launch_primbound_##T(const PairHdr *, PrimRec *, const int32_t *, int, int, double, const double *, hipStream_t);
 PB(00) PB(10) PB(11) PB(20) PB(21) PB(22)
 #undef PB
@@ -255,7 +256,7 @@ typedef void (*eri_fn)(const QuartetArgs &, unsigned, hipStream_t);
 typedef void (*eval_fn)(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *,
                         double *, hipStream_t);
 typedef void (*schwarz_fn)(const PairHdr *, const PrimRec *, const int32_t *, int, int, double, const double *,
-                           double *, hipStream_t);
+                           double *, double *, hipStream_t);
 
 // class index cb(cb+1)/2 + ck, pair classes ss ps pp ds dp dd
 static const eri_fn k_eri_tab[21] = {
@@ -445,15 +446,18 @@ extern "C" hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, co
         shd[s].off = shells[s].prim_off;
     }
     hipStream_t st = (hipStream_t)stream;
+    // temporaries are stream-ordered (hipFreeAsync does not wait for work of
+    // other streams, unlike hipFree, so a pair build never stalls builds that
+    // run concurrently on other streams)
     int32_t *d_shA = nullptr, *d_shB = nullptr;
     ShellDev *d_sh = nullptr;
     double *d_ex = nullptr, *d_cn = nullptr;
     auto cleanup = [&]() {
-        hipFree(d_shA);
-        hipFree(d_shB);
-        hipFree(d_sh);
-        hipFree(d_ex);
-        hipFree(d_cn);
+        if (d_shA) hipFreeAsync(d_shA, st);
+        if (d_shB) hipFreeAsync(d_shB, st);
+        if (d_sh) hipFreeAsync(d_sh, st);
+        if (d_ex) hipFreeAsync(d_ex, st);
+        if (d_cn) hipFreeAsync(d_cn, st);
     };
 #define ALLOC(ptr, bytes)                                                        \
     do {                                                                         \
@@ -462,16 +466,33 @@ extern "C" hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, co
             return fail(HFX_ENOMEM, "device allocation of pair data failed");    \
         }                                                                        \
     } while (0)
+#define ALLOC_TMP(ptr, bytes)                                                              \
+    do {                                                                                   \
+        if (hipMallocAsync((void **)&(ptr), (bytes), st) != hipSuccess) {                  \
+            cleanup();                                                                     \
+            return fail(HFX_ENOMEM, "device allocation of pair-build temporaries failed");  \
+        }                                                                                  \
+    } while (0)
     ALLOC(P->d_hdr, npair * sizeof(PairHdr));
     ALLOC(P->d_prim, std::max<int64_t>(rec, 1) * sizeof(PrimRec));
     ALLOC(P->d_Q, npair * sizeof(double));
-    ALLOC(d_shA, npair * sizeof(int32_t));
-    ALLOC(d_shB, npair * sizeof(int32_t));
-    ALLOC(d_sh, nshell * sizeof(ShellDev));
-    ALLOC(d_ex, std::max<int64_t>(nprim_tot, 1) * sizeof(double));
-    ALLOC(d_cn, std::max<int64_t>(nprim_tot, 1) * sizeof(double));
+    ALLOC(P->d_E, npair * sizeof(double));
+    ALLOC(P->d_part, 2 * PCHECK_BLOCKS * sizeof(double));
+    ALLOC(P->d_count, NCOUNT * sizeof(unsigned long long));
+    ALLOC(P->d_class_ids, npair * sizeof(int32_t));
+    ALLOC_TMP(d_shA, npair * sizeof(int32_t));
+    ALLOC_TMP(d_shB, npair * sizeof(int32_t));
+    ALLOC_TMP(d_sh, nshell * sizeof(ShellDev));
+    ALLOC_TMP(d_ex, std::max<int64_t>(nprim_tot, 1) * sizeof(double));
+    ALLOC_TMP(d_cn, std::max<int64_t>(nprim_tot, 1) * sizeof(double));
 #undef ALLOC
-    P->dev_bytes = npair * (sizeof(PairHdr) + sizeof(double)) + rec * sizeof(PrimRec);
+#undef ALLOC_TMP
+    for (auto &ev : P->ev)
+        if (hipEventCreate(&ev) != hipSuccess) {
+            cleanup();
+            return fail(HFX_EDEVICE, "hipEventCreate failed");
+        }
+    P->dev_bytes = npair * (sizeof(PairHdr) + 2 * sizeof(double)) + rec * sizeof(PrimRec);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpyAsync(P->d_hdr, hdr.data(), npair * sizeof(PairHdr), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_shA, shA.data(), npair * sizeof(int32_t), hipMemcpyHostToDevice, st);
@@ -479,6 +500,15 @@ extern "C" hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, co
     if (e == hipSuccess) e = hipMemcpyAsync(d_sh, shd.data(), nshell * sizeof(ShellDev), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_ex, P->exps.data(), nprim_tot * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_cn, P->cn.data(), nprim_tot * sizeof(double), hipMemcpyHostToDevice, st);
+    {
+        // pair ids of every pair class, concatenated in class order (uploaded once)
+        std::vector<int32_t> ids;
+        ids.reserve(npair);
+        for (int c = 0; c < 6; ++c) ids.insert(ids.end(), P->class_ids[c].begin(), P->class_ids[c].end());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P->d_class_ids, ids.data(), npair * sizeof(int32_t), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host vector dies here
+    }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_pairdata, dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st, P->d_hdr, d_shA,
                            d_shB, d_sh, d_ex, d_cn, npair, P->d_prim);
@@ -501,21 +531,31 @@ hfx_pairs_s::~hfx_pairs_s() {
     hipFree(d_hdr);
     hipFree(d_prim);
     hipFree(d_Q);
+    hipFree(d_E);
     hipFree(d_prim32);
     drop_lists();
     hipFree(d_count);
+    hipFree(d_part);
+    hipFree(d_class_ids);
+    for (auto &e : ev)
+        if (e) hipEventDestroy(e);
 }
 
 void hfx_pairs_s::drop_lists() {
-    for (auto &c : lists) {
-        hipFree(c.d_ids);
-        hipFree(c.d_Q);
-        hipFree(c.d_grp);
-        hipFree(c.d_goff);
-        hipFree(c.d_gnp);
-        c = ClassList();
-    }
+    for (ClassList *set : {lists, mlists})
+        for (int i = 0; i < 6; ++i) {
+            ClassList &c = set[i];
+            hipFree(c.d_ids);
+            hipFree(c.d_Q);
+            hipFree(c.d_grp);
+            hipFree(c.d_goff);
+            hipFree(c.d_gnp);
+            hipFree(c.d_A);
+            hipFree(c.d_gA);
+            c = ClassList();
+        }
     lists_valid = false;
+    mlists_valid = false;
 }
 
 extern "C" void hfx_pairs_destroy(hfx_pairs p) { delete p; }
@@ -530,28 +570,21 @@ hfx_status compute_bounds(hfx_pairs p, const hfx_opts *o, hipStream_t st) {
     const double om2 = op ? o->omega * o->omega : 0.0;
     if (p->have_Q && p->q_op == op && p->q_om2 == om2) return HFX_OK;
     p->drop_lists();
-    int32_t *d_ids = nullptr;
-    size_t mx = 0;
-    for (int c = 0; c < 6; ++c) mx = std::max(mx, p->class_ids[c].size());
-    HIPCHK(hipMalloc(&d_ids, std::max<size_t>(mx, 1) * sizeof(int32_t) * 6));
     size_t off = 0;
     for (int c = 0; c < 6; ++c) {
         const auto &ids = p->class_ids[c];
         if (ids.empty()) continue;
-        hipError_t e = hipMemcpyAsync(d_ids + off, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) {
-            hipFree(d_ids);
-            return fail(HFX_EDEVICE, std::string("bounds copy: ") + hipGetErrorString(e));
-        }
-        k_schwarz_tab[c](p->d_hdr, p->d_prim, d_ids + off, (int)ids.size(), op, om2, p->d_boys, p->d_Q, st);
-        k_primbound_tab[c](p->d_hdr, p->d_prim, d_ids + off, (int)ids.size(), op, om2, p->d_boys, st);
-        off += mx;
+        k_schwarz_tab[c](p->d_hdr, p->d_prim, p->d_class_ids + off, (int)ids.size(), op, om2, p->d_boys, p->d_Q,
+                         p->d_E, st);
+        k_primbound_tab[c](p->d_hdr, p->d_prim, p->d_class_ids + off, (int)ids.size(), op, om2, p->d_boys, st);
+        off += ids.size();
     }
     hipError_t e = hipGetLastError();
     p->Q.resize(p->npair);
+    p->E.resize(p->npair);
     if (e == hipSuccess) e = hipMemcpyAsync(p->Q.data(), p->d_Q, p->npair * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->E.data(), p->d_E, p->npair * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFree(d_ids);
     if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("bounds: ") + hipGetErrorString(e));
     p->have_Q = true;
     p->q_op = op;
@@ -577,10 +610,33 @@ hfx_status ensure_prim32(hfx_pairs p, hipStream_t st) {
 
 // Kept pairs of every class sorted by (primitive-pair count, -Q, id); groups =
 // runs of equal primitive-pair count, so every lane of a block loops the same
-// number of ket primitive pairs.
-hfx_status build_lists(hfx_pairs p, double tau, hipStream_t st) {
-    if (p->lists_valid && p->list_tau == tau) return HFX_OK;
-    p->drop_lists();
+// number of ket primitive pairs.  Mixed-precision lists are grouped by
+// (primitive-pair count, bin of A = E/Q) so that a group's largest A, which
+// sets its FP32/FP64 split, is close to that of each of its pairs.
+static int amp_bin(double A) { return A <= 4.0 ? 0 : A <= 32.0 ? 1 : A <= 256.0 ? 2 : 3; }
+
+static double amp_of(hfx_pairs p, int32_t id) {
+    const double q = p->Q[id];
+    return q > 0.0 ? std::max(1.0, p->E[id] / q) : 1.0;
+}
+
+const ClassList *class_lists(hfx_pairs p, bool mixed) { return mixed ? p->mlists : p->lists; }
+
+hfx_status build_lists(hfx_pairs p, double tau, bool mixed, hipStream_t st) {
+    if (!mixed && p->lists_valid && p->list_tau == tau) return HFX_OK;
+    if (mixed && p->mlists_valid && p->mlist_tau == tau) return HFX_OK;
+    ClassList *set = mixed ? p->mlists : p->lists;
+    for (int c = 0; c < 6; ++c) {
+        ClassList &L = set[c];
+        hipFree(L.d_ids);
+        hipFree(L.d_Q);
+        hipFree(L.d_grp);
+        hipFree(L.d_goff);
+        hipFree(L.d_gnp);
+        hipFree(L.d_A);
+        hipFree(L.d_gA);
+        L = ClassList();
+    }
     double qmax = 0.0;
     for (double q : p->Q) qmax = std::max(qmax, q);
     p->qmax = qmax;
@@ -588,27 +644,35 @@ hfx_status build_lists(hfx_pairs p, double tau, hipStream_t st) {
         std::vector<int32_t> ids;
         for (int32_t id : p->class_ids[c])
             if (p->Q[id] * qmax >= tau) ids.push_back(id);
+        auto key = [&](int32_t x) { return p->hdr_host[x].n * 4 + (mixed ? amp_bin(amp_of(p, x)) : 0); };
         std::sort(ids.begin(), ids.end(), [&](int32_t x, int32_t y) {
-            const int nx = p->hdr_host[x].n, ny = p->hdr_host[y].n;
-            if (nx != ny) return nx < ny;
+            const int kx = key(x), ky = key(y);
+            if (kx != ky) return kx < ky;
             if (p->Q[x] != p->Q[y]) return p->Q[x] > p->Q[y];
             return x < y;
         });
-        ClassList &L = p->lists[c];
+        ClassList &L = set[c];
         L.n = (int)ids.size();
         if (!L.n) continue;
-        std::vector<double> q(L.n);
+        std::vector<double> q(L.n), A, gA;
         std::vector<int32_t> grp(L.n);
+        std::vector<int> gkey;
         L.goff.clear();
         L.gnp.clear();
         for (int i = 0; i < L.n; ++i) {
             q[i] = p->Q[ids[i]];
-            const int np = p->hdr_host[ids[i]].n;
-            if (L.gnp.empty() || L.gnp.back() != np) {
-                L.gnp.push_back(np);
+            const int k = key(ids[i]);
+            if (gkey.empty() || gkey.back() != k) {
+                gkey.push_back(k);
+                L.gnp.push_back(p->hdr_host[ids[i]].n);
                 L.goff.push_back(i);
+                if (mixed) gA.push_back(1.0);
             }
             grp[i] = (int)L.gnp.size() - 1;
+            if (mixed) {
+                A.push_back(amp_of(p, ids[i]));
+                gA.back() = std::max(gA.back(), A.back());
+            }
         }
         L.goff.push_back(L.n);
         L.ngrp = (int)L.gnp.size();
@@ -622,26 +686,38 @@ hfx_status build_lists(hfx_pairs p, double tau, hipStream_t st) {
         HIPCHK(hipMemcpyAsync(L.d_grp, grp.data(), L.n * sizeof(int32_t), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(L.d_goff, L.goff.data(), L.goff.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(L.d_gnp, L.gnp.data(), L.gnp.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        if (mixed) {
+            HIPCHK(hipMalloc(&L.d_A, L.n * sizeof(double)));
+            HIPCHK(hipMalloc(&L.d_gA, gA.size() * sizeof(double)));
+            HIPCHK(hipMemcpyAsync(L.d_A, A.data(), L.n * sizeof(double), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(L.d_gA, gA.data(), gA.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        }
+        // the host vectors must outlive the copies
+        HIPCHK(hipStreamSynchronize(st));
         L.h_ids = std::move(ids);
         L.h_Q = std::move(q);
         L.h_grp = std::move(grp);
     }
     HIPCHK(hipStreamSynchronize(st));
-    p->lists_valid = true;
-    p->list_tau = tau;
+    if (mixed) {
+        p->mlists_valid = true;
+        p->mlist_tau = tau;
+    } else {
+        p->lists_valid = true;
+        p->list_tau = tau;
+    }
     return HFX_OK;
 }
 
-hfx_status check_P(const double *P, int64_t n, int64_t ld, hipStream_t st) {
-    const int nb = (int)std::min<int64_t>(1024, (n * n + 255) / 256);
-    double *part = nullptr;
-    HIPCHK(hipMalloc(&part, 2 * nb * sizeof(double)));
+// part: device, 2 * PCHECK_BLOCKS doubles (every block writes its two
+// entries, so nothing needs clearing).
+hfx_status check_P(const double *P, int64_t n, int64_t ld, hipStream_t st, double *part) {
+    const int nb = (int)std::min<int64_t>(PCHECK_BLOCKS, (n * n + 255) / 256);
     hipLaunchKernelGGL(k_asym, dim3(nb), dim3(256), 0, st, P, n, ld, part);
-    std::vector<double> h(2 * nb);
+    double h[2 * PCHECK_BLOCKS];
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, part, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFree(part);
     if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("P check: ") + hipGetErrorString(e));
     double asym = 0.0, mx = 0.0;
     for (int b = 0; b < nb; ++b) {
@@ -663,9 +739,10 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, double *J, in
     const int op = kernel_op(o);
     const bool mixed = (o->prec == HFX_PREC_MIXED);
     const double inf = HUGE_VAL;
+    const ClassList *lists = class_lists(p, mixed);
     for (int cb = 0; cb < 6; ++cb)
         for (int ck = 0; ck <= cb; ++ck) {
-            const ClassList &B = p->lists[cb], &Kl = p->lists[ck];
+            const ClassList &B = lists[cb], &Kl = lists[ck];
             const int ci = cb * (cb + 1) / 2 + ck;
             if (ev) HIPCHK(hipEventRecord(ev[ci], st));
             if (!B.n || !Kl.n || shard >= B.n) continue;
@@ -704,16 +781,20 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, double *J, in
             const int64_t nblk = (int64_t)((B.n - shard + nshards - 1) / nshards) * Kl.ngrp * a.nsub;
             if (nblk > (int64_t)UINT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
             a.om = op ? o->omega : 0.0;
-            // FP64: Q_p Q_q >= max(tau, cut) in mixed mode, >= tau otherwise
-            a.tau = mixed ? std::max(o->tau, o->mixed_cut) : o->tau;
+            // FP64: Q_p Q_q >= tau, and in mixed mode E_p E_q >= cut as well
+            // (split per block in ket_cut)
+            a.tau = o->tau;
             a.tau_hi = inf;
+            a.part = mixed ? 1 : 0;
+            a.mixed_cut = o->mixed_cut;
+            a.bra_A = B.d_A;
+            a.ket_gA = Kl.d_gA;
             a.count = count ? count + 4 * ci : nullptr;
             (J ? k_erijk_tab : k_eri_tab)[ci](a, (unsigned)nblk, st);
             HIPCHK(hipGetLastError());
-            if (mixed && o->mixed_cut > o->tau) {
-                // FP32: tau <= Q_p Q_q < cut
-                a.tau = o->tau;
-                a.tau_hi = o->mixed_cut;
+            if (mixed && o->mixed_cut > 0.0) {
+                // FP32: Q_p Q_q >= tau and E_p E_q < cut
+                a.part = 2;
                 a.count = count ? count + 4 * ci + 2 : nullptr;
                 (J ? k_erijk32_tab : k_eri32_tab)[ci](a, (unsigned)nblk, st);
                 HIPCHK(hipGetLastError());
@@ -741,7 +822,7 @@ static bool overlaps(const double *x, const double *y, int64_t n, int64_t ld) {
 
 hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
                              const hfx_opts *o, int shard, int nshards, void *stream, hfx_stats *st_out,
-                             double *J_dev) {
+                             double *J_dev, const Workspace *ws_in) {
     auto t0 = std::chrono::steady_clock::now();
     if (!p) return fail(HFX_EINVAL, "pairs is NULL");
     if (!P_dev || !K_dev) return fail(HFX_EINVAL, "P or K is NULL");
@@ -754,25 +835,40 @@ hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, in
     if (J_dev && (overlaps(J_dev, P_dev, n, ld) || overlaps(J_dev, K_dev, n, ld)))
         return fail(HFX_EINVAL, "J aliases P or K");
     hipStream_t st = (hipStream_t)stream;
-    s = check_P(P_dev, n, ld, st);
-    if (s != HFX_OK) return s;
-    s = compute_bounds(p, o, st);
-    if (s != HFX_OK) return s;
-    s = build_lists(p, o->tau, st);
-    if (s != HFX_OK) return s;
-    if (o->prec == HFX_PREC_MIXED) {
-        s = ensure_prim32(p, st);
-        if (s != HFX_OK) return s;
+    const Workspace ws = ws_in ? *ws_in : Workspace{p->d_part, p->d_count};
+    if (ws_in) {
+        // nothing may be allocated: the handle must hold what these options need
+        const int op = kernel_op(o);
+        const double om2 = op ? o->omega * o->omega : 0.0;
+        if (!(p->have_Q && p->q_op == op && p->q_om2 == om2))
+            return fail(HFX_EINVAL, "Schwarz bounds for this kernel are not resident in the handle "
+                                    "(run hfx_build_K once with the same options first)");
+        const bool mx = o->prec == HFX_PREC_MIXED;
+        if (!(mx ? (p->mlists_valid && p->mlist_tau == o->tau) : (p->lists_valid && p->list_tau == o->tau)))
+            return fail(HFX_EINVAL, "screening lists for this tau are not resident in the handle "
+                                    "(run hfx_build_K once with the same options first)");
+        if (o->prec == HFX_PREC_MIXED && !p->prim32_valid)
+            return fail(HFX_EINVAL, "FP32 records are not resident in the handle "
+                                    "(run hfx_build_K once in mixed precision first)");
     }
-    if (!p->d_count) HIPCHK(hipMalloc(&p->d_count, 4 * HFX_NCLASS * sizeof(unsigned long long)));
-    unsigned long long *cnt = st_out ? p->d_count : nullptr;
-    if (cnt) hipLaunchKernelGGL(k_fill_u64, dim3(2), dim3(64), 0, st, cnt, 4 * HFX_NCLASS);
+    s = check_P(P_dev, n, ld, st, ws.part);
+    if (s != HFX_OK) return s;
+    if (!ws_in) {
+        s = compute_bounds(p, o, st);
+        if (s != HFX_OK) return s;
+        s = build_lists(p, o->tau, o->prec == HFX_PREC_MIXED, st);
+        if (s != HFX_OK) return s;
+        if (o->prec == HFX_PREC_MIXED) {
+            s = ensure_prim32(p, st);
+            if (s != HFX_OK) return s;
+        }
+    }
+    unsigned long long *cnt = st_out ? ws.count : nullptr;
+    if (cnt) hipLaunchKernelGGL(k_fill_u64, dim3(2), dim3(64), 0, st, cnt, NCOUNT);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, K_dev, n, ld);
     if (J_dev) hipLaunchKernelGGL(k_fill, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, J_dev, n, ld);
     HIPCHK(hipGetLastError());
-    hipEvent_t ev[HFX_NCLASS + 1] = {};
-    if (st_out)
-        for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    hipEvent_t *ev = p->ev;  // created with the handle (one build per handle at a time)
     s = launch_classes(p, P_dev, K_dev, J_dev, ld, o, st, cnt, shard, nshards, st_out ? ev : nullptr);
     if (s != HFX_OK) return s;
     const unsigned g = (unsigned)((n + 15) / 16);
@@ -780,8 +876,8 @@ hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, in
     if (J_dev) hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(16, 16), 0, st, J_dev, n, ld);
     HIPCHK(hipGetLastError());
     if (st_out) {
-        std::vector<unsigned long long> h(4 * HFX_NCLASS);
-        HIPCHK(hipMemcpyAsync(h.data(), cnt, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        unsigned long long h[NCOUNT];
+        HIPCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         std::memset(st_out, 0, sizeof(*st_out));
         float ms = 0.f;
@@ -808,7 +904,6 @@ hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, in
             st_out->prim_quartets += (int64_t)npq;
             st_out->flops += st_out->class_flops[c];
         }
-        for (auto &e : ev) hipEventDestroy(e);
         st_out->latency_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return HFX_OK;
@@ -883,16 +978,19 @@ extern "C" hfx_status hfx_eval_quartets(hfx_pairs p, const hfx_opts *o, int64_t 
         }
         int32_t *d_bk = nullptr;
         double *d_out = nullptr;
-        HIPCHK(hipMalloc(&d_bk, bk.size() * sizeof(int32_t)));
-        HIPCHK(hipMalloc(&d_out, (size_t)m * nout * sizeof(double)));
+        HIPCHK(hipMallocAsync((void **)&d_bk, bk.size() * sizeof(int32_t), st));
+        if (hipMallocAsync((void **)&d_out, (size_t)m * nout * sizeof(double), st) != hipSuccess) {
+            hipFreeAsync(d_bk, st);
+            return fail(HFX_ENOMEM, "eval: device allocation failed");
+        }
         HIPCHK(hipMemcpyAsync(d_bk, bk.data(), bk.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
         k_eval_tab[c](p->d_hdr, p->d_prim, d_bk, m, op, om2, p->d_boys, d_out, st);
         std::vector<double> h((size_t)m * nout);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+        hipFreeAsync(d_bk, st);
+        hipFreeAsync(d_out, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
-        hipFree(d_bk);
-        hipFree(d_out);
         if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("eval: ") + hipGetErrorString(e));
         // canonical block [A][B][C][D] -> caller order [I][J][K][L]
         for (int i = 0; i < m; ++i) {

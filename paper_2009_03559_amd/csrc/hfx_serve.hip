@@ -15,7 +15,9 @@
 // pair handle is not busy, so requests that arrive while others run are
 // admitted as slots and memory free up, and their kernels overlap on the
 // device (continuous batching).  Pair data stays resident in its handle
-// across the SCF iterations of a request.
+// across the SCF iterations of a request.  A build allocates and frees no
+// device memory once its handle holds its bounds and lists (a hipFree would
+// wait for the kernels of every stream and serialise the workers).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -148,9 +150,9 @@ static void make_jobs(ClassJobs &cj, int ci, int nsys, hfx_pairs const *p, const
     const bool mixed = (o->prec == HFX_PREC_MIXED);
     std::vector<std::pair<double, int>> order;
     for (int s = 0; s < nsys; ++s) {
-        const ClassList &B = p[s]->lists[cb], &Kl = p[s]->lists[ck];
+        const ClassList &B = class_lists(p[s], mixed)[cb], &Kl = class_lists(p[s], mixed)[ck];
         if (!B.n || !Kl.n) continue;
-        if (f32 && !(mixed && o->mixed_cut > o->tau)) continue;
+        if (f32 && !(mixed && o->mixed_cut > 0.0)) continue;
         order.push_back({-(double)B.n * (double)Kl.n, s});  // largest first
     }
     std::sort(order.begin(), order.end());
@@ -158,7 +160,7 @@ static void make_jobs(ClassJobs &cj, int ci, int nsys, hfx_pairs const *p, const
     cj.vtotal = 0;
     for (auto &os : order) {
         const int s = os.second;
-        const ClassList &B = p[s]->lists[cb], &Kl = p[s]->lists[ck];
+        const ClassList &B = class_lists(p[s], mixed)[cb], &Kl = class_lists(p[s], mixed)[ck];
         BatchJob j;
         std::memset(&j, 0, sizeof(j));
         QuartetArgs &a = j.a;
@@ -188,13 +190,14 @@ static void make_jobs(ClassJobs &cj, int ci, int nsys, hfx_pairs const *p, const
         a.P = P[s];
         a.K = K[s];
         a.ld = ld[s];
-        if (!f32) {
-            a.tau = mixed ? std::max(o->tau, o->mixed_cut) : o->tau;
-            a.tau_hi = HUGE_VAL;
-        } else {
-            a.tau = o->tau;
-            a.tau_hi = o->mixed_cut;
-        }
+        // FP64 side (all of it unless mixed) and FP32 side of the per-block
+        // split on the FP32 error scale (see ket_cut)
+        a.tau = o->tau;
+        a.tau_hi = HUGE_VAL;
+        a.part = mixed ? (f32 ? 2 : 1) : 0;
+        a.mixed_cut = o->mixed_cut;
+        a.bra_A = B.d_A;
+        a.ket_gA = Kl.d_gA;
         a.count = cnt ? cnt[s] + 4 * ci + (f32 ? 2 : 0) : nullptr;
         int gmax = 1;
         for (size_t g = 0; g + 1 < Kl.goff.size(); ++g) gmax = std::max(gmax, Kl.goff[g + 1] - Kl.goff[g]);
@@ -293,18 +296,17 @@ hfx_status batch_impl(int32_t nsys, const hfx_pairs *p, const double *const *P, 
             if (p[j] == p[i]) return fail(HFX_EINVAL, "a pair handle appears twice in one batch");
         const int64_t n = p[i]->nbf;
         if (ld[i] < n) return fail(HFX_EINVAL, "ld < n_bf");
-        s = check_P(P[i], n, ld[i], st);
+        s = check_P(P[i], n, ld[i], st, p[i]->d_part);
         if (s != HFX_OK) return s;
         s = compute_bounds(p[i], o, st);
         if (s != HFX_OK) return s;
-        s = build_lists(p[i], o->tau, st);
+        s = build_lists(p[i], o->tau, o->prec == HFX_PREC_MIXED, st);
         if (s != HFX_OK) return s;
         if (o->prec == HFX_PREC_MIXED) {
             s = ensure_prim32(p[i], st);
             if (s != HFX_OK) return s;
         }
-        if (!p[i]->d_count) HIPCHK(hipMalloc(&p[i]->d_count, 4 * HFX_NCLASS * sizeof(unsigned long long)));
-        launch_fill_u64(p[i]->d_count, 4 * HFX_NCLASS, st);
+        launch_fill_u64(p[i]->d_count, NCOUNT, st);
     }
     unsigned long long *head = nullptr;
     HIPCHK(hipMalloc(&head, 2 * sizeof(unsigned long long)));
@@ -344,7 +346,8 @@ hfx_status batch_impl(int32_t nsys, const hfx_pairs *p, const double *const *P, 
                     int cb = 0;
                     while ((cb + 1) * (cb + 2) / 2 <= ci) ++cb;
                     const int ck = ci - cb * (cb + 1) / 2;
-                    any |= p[i]->lists[cb].n && p[i]->lists[ck].n;
+                    const ClassList *ls = class_lists(p[i], o->prec == HFX_PREC_MIXED);
+                    any |= ls[cb].n && ls[ck].n;
                 }
                 tune[f * HFX_NCLASS + ci] = t;
                 if (any) {
@@ -370,7 +373,7 @@ hfx_status batch_impl(int32_t nsys, const hfx_pairs *p, const double *const *P, 
     BatchRun run;
     for (int f = 0; f < 2; ++f)
         for (int ci = 0; ci < HFX_NCLASS; ++ci) {
-            if (f == 1 && !(o->prec == HFX_PREC_MIXED && o->mixed_cut > o->tau)) continue;
+            if (f == 1 && !(o->prec == HFX_PREC_MIXED && o->mixed_cut > 0.0)) continue;
             const Tune &t = tune[f * HFX_NCLASS + ci];
             ClassJobs cj;
             make_jobs(cj, ci, nsys, p, P, K, ld, o, f == 1, cnt.data(), t.tq, k_nsplit_tab[f][ci](), 1);
@@ -518,6 +521,10 @@ extern "C" hfx_status hfx_server_create(int64_t hbm_budget_bytes, int32_t max_in
     std::unique_ptr<hfx_server_s> s(new hfx_server_s());
     s->budget = hbm_budget_bytes;
     s->max_inflight = max_inflight;
+    // capacity of the queue of waiting requests (submit returns HFX_EBUSY when
+    // it is full); HFX_SERVER_QUEUE overrides the default of 4096
+    if (const char *e = std::getenv("HFX_SERVER_QUEUE"))
+        if (*e) s->max_queue = (size_t)std::max(1ll, std::atoll(e));
     if (hipGetDevice(&s->dev) != hipSuccess) return fail(HFX_EDEVICE, "hipGetDevice failed");
     for (int i = 0; i < max_inflight; ++i) s->workers.emplace_back(&hfx_server_s::worker, s.get());
     *out = s.release();

@@ -92,7 +92,7 @@ def test_batch_empty():
 def test_served_equals_solo_in_mix():
     """Requests of several systems, three SCF-like iterations each with a
     perturbed P, submitted together: four workers run them concurrently; each
-    K equals the system's K built alone."""
+    K equals the system's K built alone and the oracle's K for the same P."""
     systems = _systems(n=6, seed=50)
     o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
     pairs = [hfx.pairs_from_system(s, o) for s in systems]
@@ -128,6 +128,8 @@ def test_served_equals_solo_in_mix():
         hfx.build_K(ps, Ps, Kref, o)
         torch.cuda.synchronize()
         assert torch.abs(K - Kref).max().item() <= 1e-12
+        Ko, _, _ = oracle.build_K(s, tau=1e-10, omega=hi.OMEGA_HSE, P=Pn)
+        assert np.abs(K.cpu().numpy() - Ko).max() <= 1e-10
     with pytest.raises(hfx.HfxError) as e:
         srv.poll(jobs[0][4])  # already collected
     assert e.value.status == hfx.HFX_ENOTFOUND
@@ -161,3 +163,39 @@ def test_server_admission_and_errors():
     assert not pend
     for i in range(1, 3):
         assert torch.abs(Ks[i] - Ks[0]).max().item() <= 1e-12
+
+
+def test_server_queue_full_is_ebusy(monkeypatch):
+    """A queue of capacity one behind one busy worker: a third quick
+    submission finds it full (HFX_EBUSY); every accepted request completes
+    with the solo K."""
+    monkeypatch.setenv("HFX_SERVER_QUEUE", "1")
+    s = hi.lattice_system(12, seed=61)
+    o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
+    pairs = [hfx.pairs_from_system(s, o) for _ in range(6)]
+    P = torch.from_numpy(s.P).cuda()
+    Ks = [torch.empty_like(P) for _ in range(6)]
+    torch.cuda.synchronize()
+    srv = hfx.Server(hbm_budget_bytes=1 << 34, max_inflight=1)
+    accepted, busy = [], 0
+    for i in range(6):
+        try:
+            accepted.append((i, srv.submit(pairs[i], P, Ks[i], o)))
+        except hfx.HfxError as e:
+            assert e.status == hfx.HFX_EBUSY
+            busy += 1
+    _say("queue of one: accepted", len(accepted), "busy", busy)
+    assert busy >= 1 and len(accepted) >= 1
+    t_end = time.time() + 60
+    pend = dict(accepted)
+    while pend and time.time() < t_end:
+        for i, t in list(pend.items()):
+            if srv.poll(t)[0]:
+                del pend[i]
+        time.sleep(0.005)
+    assert not pend
+    Kref = torch.empty_like(P)
+    hfx.build_K(hfx.pairs_from_system(s, o), P, Kref, o)
+    torch.cuda.synchronize()
+    for i, _ in accepted:
+        assert torch.abs(Ks[i] - Kref).max().item() <= 1e-12
