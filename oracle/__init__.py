@@ -58,6 +58,9 @@ def lib():
         L.oracle_build_JK.restype = ctypes.c_int
         L.oracle_build_JK.argtypes = basis + [_f64p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                               _f64p, _f64p, _f64p, _i64p]
+        L.oracle_build_JK_density.restype = ctypes.c_int
+        L.oracle_build_JK_density.argtypes = basis + [_f64p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                      ctypes.c_void_p, _f64p, _f64p, _i64p]
         L.oracle_digest_list.restype = ctypes.c_int
         L.oracle_digest_list.argtypes = basis + [_f64p, ctypes.c_double, ctypes.c_int64, _i64p,
                                                  ctypes.c_int, _f64p]
@@ -158,6 +161,28 @@ def build_JK(sys, tau=1e-10, omega=0.0, nthreads=0, P=None):
         raise ValueError("oracle_build_JK: invalid basis")
     return J, K, Q[:npair], dict(quartets=int(cnt[0]), prim_quartets=int(cnt[1]),
                                   per_class=cnt[2:].copy())
+
+
+def build_K_density(sys, tau=1e-10, omega=0.0, nthreads=0, P=None, coulomb=False):
+    """Exchange build with the density-weighted test added to the Schwarz
+    test (a quartet passing Q_IJ Q_KL >= tau is computed iff also
+    Q_IJ Q_KL D >= tau, D = largest |P| over its digestion's shell blocks).
+    coulomb=True: J as well (D then includes the blocks (I,J) and (K,L)).
+    Returns (K, Q, counts), or (J, K, Q, counts) with coulomb=True."""
+    n = sys.nbf
+    P = np.ascontiguousarray(sys.P if P is None else P, dtype=np.float64)
+    K = np.zeros((n, n), dtype=np.float64)
+    J = np.zeros((n, n), dtype=np.float64) if coulomb else None
+    npair = sys.nshell * (sys.nshell + 1) // 2
+    Q = np.zeros(max(npair, 1), dtype=np.float64)
+    cnt = np.zeros(23, dtype=np.int64)
+    jp = J.ctypes.data_as(ctypes.c_void_p) if coulomb else None
+    rc = lib().oracle_build_JK_density(*_basis_args(sys), P.ravel(), float(tau), float(omega), int(nthreads),
+                                       jp, K.ravel(), Q, cnt)
+    if rc:
+        raise ValueError("oracle_build_JK_density: invalid basis")
+    c = dict(quartets=int(cnt[0]), prim_quartets=int(cnt[1]), per_class=cnt[2:].copy())
+    return (J, K, Q[:npair], c) if coulomb else (K, Q[:npair], c)
 
 
 def digest_list(sys, pairs_pq: np.ndarray, omega=0.0, nthreads=0, P=None) -> np.ndarray:

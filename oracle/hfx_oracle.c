@@ -562,10 +562,47 @@ int oracle_class_index(int la, int lb, int lc, int ld) {
     return cb * (cb + 1) / 2 + ck;
 }
 
+/* Largest |P_xy| over the functions x of shell X and y of shell Y, for every
+ * shell pair (n_shell x n_shell, row-major).                                */
+static double *shell_pmax(int nshell, const int *bfo, const double *P, int64_t n) {
+    double *M = malloc(sizeof(double) * (size_t)nshell * (nshell > 0 ? nshell : 1));
+    for (int X = 0; X < nshell; X++)
+        for (int Y = 0; Y < nshell; Y++) {
+            double m = 0;
+            for (int x = bfo[X]; x < bfo[X + 1]; x++)
+                for (int y = bfo[Y]; y < bfo[Y + 1]; y++) {
+                    double a = fabs(P[(int64_t)x * n + y]);
+                    if (a > m) m = a;
+                }
+            M[(size_t)X * nshell + Y] = m;
+        }
+    return M;
+}
+
+/* Density weight of the unique quartet (IJ|KL): the largest |P| over the
+ * shell blocks that multiply its integrals in the digestion.  Exchange: the
+ * blocks (I,K), (I,L), (J,K), (J,L); with the Coulomb matrix also (I,J) and
+ * (K,L).  Reading of the screening the paper adds after the Schwarz test
+ * (Sec. 3, NAO screening): an integral that can change no element of K (or
+ * J) by tau or more is skipped.                                             */
+static double density_weight(const double *M, int nshell, int I, int J, int K, int L, int coulomb) {
+    double d = M[(size_t)I * nshell + K];
+    double v;
+    v = M[(size_t)I * nshell + L]; if (v > d) d = v;
+    v = M[(size_t)J * nshell + K]; if (v > d) d = v;
+    v = M[(size_t)J * nshell + L]; if (v > d) d = v;
+    if (coulomb) {
+        v = M[(size_t)I * nshell + J]; if (v > d) d = v;
+        v = M[(size_t)K * nshell + L]; if (v > d) d = v;
+    }
+    return d;
+}
+
 static int build_JK(const double *xyz, int nshell, const int32_t *atom, const int32_t *l,
                     const int32_t *nprim, const int32_t *off, const double *exps,
                     const double *coefs, const double *P, double tau, double omega,
-                    int nthreads, double *Jout, double *K, double *Q_out, int64_t *counts) {
+                    int nthreads, double *Jout, double *K, double *Q_out, int64_t *counts,
+                    int density) {
     basis_t B; double *cn;
     if (setup_basis(&B, xyz, nshell, atom, l, nprim, off, exps, coefs, &cn)) return 1;
     int *bfo = malloc(sizeof(int) * (nshell + 1));
@@ -582,6 +619,7 @@ static int build_JK(const double *xyz, int nshell, const int32_t *atom, const in
     for (int64_t p = 0; p < npair; p++) if (Q[p] > qmax) qmax = Q[p];
     memset(K, 0, sizeof(double) * n * n);
     if (Jout) memset(Jout, 0, sizeof(double) * n * n);
+    double *M = density ? shell_pmax(nshell, bfo, P, n) : NULL;
     int64_t cnt[2 + 21] = {0};
     #pragma omp parallel
     {
@@ -598,6 +636,7 @@ static int build_JK(const double *xyz, int nshell, const int32_t *atom, const in
                 if (!(Q[q] * qmax >= tau)) continue;
                 if (!(Q[p] * Q[q] >= tau)) continue;
                 int Kk = pair_I(q), Ll = (int)(q - (int64_t)Kk * (Kk + 1) / 2);
+                if (M && !(Q[p] * Q[q] * density_weight(M, nshell, I, J, Kk, Ll, Jout != NULL) >= tau)) continue;
                 shell_quartet(&B, I, J, Kk, Ll, omega, W, blk);
                 digest(blk, I, J, Kk, Ll, bfo, l, P, n, Kp);
                 if (Jp) digest_J(blk, I, J, Kk, Ll, bfo, l, P, n, Jp);
@@ -626,7 +665,7 @@ static int build_JK(const double *xyz, int nshell, const int32_t *atom, const in
         }
     if (Q_out) memcpy(Q_out, Q, sizeof(double) * npair);
     if (counts) memcpy(counts, cnt, sizeof(cnt));
-    free(Q); free(bfo); free(cn);
+    free(Q); free(bfo); free(cn); free(M);
     return 0;
 }
 
@@ -635,7 +674,18 @@ int oracle_build_K(const double *xyz, int nshell, const int32_t *atom, const int
                    const double *coefs, const double *P, double tau, double omega,
                    int nthreads, double *K, double *Q_out, int64_t *counts) {
     return build_JK(xyz, nshell, atom, l, nprim, off, exps, coefs, P, tau, omega, nthreads,
-                    NULL, K, Q_out, counts);
+                    NULL, K, Q_out, counts, 0);
+}
+
+/* Exchange (and, with J non-NULL, Coulomb) build with the density-weighted
+ * test added to the Schwarz test: a unique quartet passing Q_IJ Q_KL >= tau
+ * is computed iff also Q_IJ Q_KL D_IJKL >= tau, D the density weight above. */
+int oracle_build_JK_density(const double *xyz, int nshell, const int32_t *atom, const int32_t *l,
+                            const int32_t *nprim, const int32_t *off, const double *exps,
+                            const double *coefs, const double *P, double tau, double omega,
+                            int nthreads, double *J, double *K, double *Q_out, int64_t *counts) {
+    return build_JK(xyz, nshell, atom, l, nprim, off, exps, coefs, P, tau, omega, nthreads,
+                    J, K, Q_out, counts, 1);
 }
 
 /* Coulomb and exchange from the same screened quartets: J_ij = sum_kl (ij|kl)
@@ -646,7 +696,7 @@ int oracle_build_JK(const double *xyz, int nshell, const int32_t *atom, const in
                     const double *coefs, const double *P, double tau, double omega,
                     int nthreads, double *J, double *K, double *Q_out, int64_t *counts) {
     return build_JK(xyz, nshell, atom, l, nprim, off, exps, coefs, P, tau, omega, nthreads,
-                    J, K, Q_out, counts);
+                    J, K, Q_out, counts, 0);
 }
 
 /* Digest an explicit list of unique shell quartets (I,J,K,L given as pair

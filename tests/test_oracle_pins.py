@@ -690,3 +690,101 @@ def test_digest_list_reproduces_build_K():
     pq = np.asarray(pq, dtype=np.int64)[rng.permutation(len(pq))]
     Kp = oracle.digest_list(s, pq, omega=0.11)
     assert np.abs(Kp + Kp.T - K).max() <= 1e-14 * np.abs(K).max()
+
+
+# ---------------------------------- density-weighted screening (next row) ----
+def _shell_pmax_np(s, P):
+    bfo = list(s.bf_offsets()) + [s.nbf]
+    n = s.nshell
+    M = np.zeros((n, n))
+    for X in range(n):
+        for Y in range(n):
+            M[X, Y] = np.abs(P[bfo[X]:bfo[X + 1], bfo[Y]:bfo[Y + 1]]).max()
+    return M
+
+
+def _density_count(s, Q, P, tau, coulomb=False):
+    """Unique quartets computed under the density-weighted rule, counted
+    directly from the Schwarz factors and the shell-block maxima of |P|."""
+    M = _shell_pmax_np(s, P)
+    n = s.nshell
+    pid = [(I, J) for I in range(n) for J in range(I + 1)]
+    qmax = Q.max()
+    keep = [p for p in range(len(pid)) if Q[p] * qmax >= tau]
+    cnt = 0
+    for a, p in enumerate(keep):
+        I, J = pid[p]
+        for q in keep[:a + 1]:
+            if not (Q[p] * Q[q] >= tau):
+                continue
+            K, L = pid[q]
+            d = max(M[I, K], M[I, L], M[J, K], M[J, L])
+            if coulomb:
+                d = max(d, M[I, J], M[K, L])
+            if Q[p] * Q[q] * d >= tau:
+                cnt += 1
+    return cnt
+
+
+@pytest.mark.parametrize("coulomb", [False, True])
+def test_density_screening_counts_and_error_bound(coulomb):
+    """The density-weighted build computes exactly the quartets the rule
+    keeps (counted independently), and differs from the Schwarz-only build by
+    at most what the dropped quartets can contribute: each value is bounded by
+    Q_IJ Q_KL and meets |P| <= D in the digestion (<= 25 functions per shell
+    pair, four images and the transpose)."""
+    s = hi.lattice_system(6, seed=23, nprim_range=(1, 3))
+    tau = 1e-7
+    if coulomb:
+        J0, K0, Q, c0 = oracle.build_JK(s, tau=tau, omega=0.11)
+        Jd, Kd, Qd, cd = oracle.build_K_density(s, tau=tau, omega=0.11, coulomb=True)
+    else:
+        K0, Q, c0 = oracle.build_K(s, tau=tau, omega=0.11)
+        Kd, Qd, cd = oracle.build_K_density(s, tau=tau, omega=0.11)
+    assert np.array_equal(Q, Qd)
+    want = _density_count(s, Q, s.P, tau, coulomb)
+    assert cd["quartets"] == want
+    assert 0 < cd["quartets"] < c0["quartets"]
+    # dropped quartets: Schwarz-kept minus density-kept
+    M = _shell_pmax_np(s, s.P)
+    n = s.nshell
+    pid = [(I, J) for I in range(n) for J in range(I + 1)]
+    qmax = Q.max()
+    bound = 0.0
+    for p in range(len(pid)):
+        if not Q[p] * qmax >= tau:
+            continue
+        I, J = pid[p]
+        for q in range(p + 1):
+            if not (Q[q] * qmax >= tau and Q[p] * Q[q] >= tau):
+                continue
+            K, L = pid[q]
+            d = max(M[I, K], M[I, L], M[J, K], M[J, L])
+            if coulomb:
+                d = max(d, M[I, J], M[K, L])
+            if not Q[p] * Q[q] * d >= tau:
+                bound += 2 * 4 * 25 * Q[p] * Q[q] * d
+    assert np.abs(Kd - K0).max() <= bound
+    assert np.abs(Kd - Kd.T).max() == 0.0
+    if coulomb:
+        assert np.abs(Jd - J0).max() <= bound
+
+
+def test_density_screening_reduces_to_schwarz_for_unit_blocks():
+    """With every shell block of |P| peaking at exactly 1 the density weight
+    is 1 and the rule is the Schwarz rule: same quartets, same K."""
+    s = hi.lattice_system(5, seed=24, nprim_range=(1, 3))
+    P = np.ones((s.nbf, s.nbf))
+    K0, Q, c0 = oracle.build_K(s, tau=1e-8, omega=0.11, P=P)
+    Kd, _, cd = oracle.build_K_density(s, tau=1e-8, omega=0.11, P=P)
+    assert cd["quartets"] == c0["quartets"]
+    assert (cd["per_class"] == c0["per_class"]).all()
+    assert np.abs(Kd - K0).max() <= 1e-14 * np.abs(K0).max()
+
+
+def test_density_screening_tau_zero_keeps_everything():
+    s = hi.config0()
+    K0, Q, c0 = oracle.build_K(s, tau=0.0, omega=0.11)
+    Kd, _, cd = oracle.build_K_density(s, tau=0.0, omega=0.11)
+    assert cd["quartets"] == c0["quartets"] == 136 * 137 // 2
+    assert np.abs(Kd - K0).max() <= 1e-14 * np.abs(K0).max()
