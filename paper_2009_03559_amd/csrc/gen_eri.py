@@ -171,24 +171,36 @@ def vrr_graph(la, lb, lc, ld, f_targets=None, policy="auto", last="auto"):
         for f in f_t:
             for e in e_t:
                 need((e, f, 0))
-        cost = sum(_node_flops(rec[n]) for n in order)
+        cost = sum(_node_cost(rec[n]) for n in order)
         if best is None or cost < best[0]:
             best = (cost, rec, order, (pol, side))
     return best[1], best[2], e_t, f_t, best[0]
 
 
+def _node_cost(r):
+    """Selection weight of a node (recurrence order, slice partitions): twice
+    its instruction count (a product-sum of t terms issues t instructions,
+    a c (v - r w) term one more)."""
+    if r[0] == "base":
+        return 1
+    n = 0
+    for p in r[1]:
+        n += 4 if p[0] in ("F2", "E2") else 2
+    return n
+
+
 def _node_flops(r):
+    """Arithmetic of one node: the products of its terms (c (v - r w) is two
+    products and a difference), plus one addition fewer than it has terms."""
     if r[0] == "base":
         return 1  # pref * G_m
     n = 0
     for p in r[1]:
-        if p[0] in ("QC", "WQ", "PA", "WP"):
-            n += 2
+        if p[0] in ("QC", "WQ", "PA", "WP", "EX", "FX"):
+            n += 1
         elif p[0] in ("F2", "E2"):
-            n += 4
-        elif p[0] in ("EX", "FX"):
-            n += 2
-    return n
+            n += 3
+    return n + len(r[1]) - 1
 
 
 def emit_vrr(em, la, lb, lc, ld, name, f_targets=None, policy="auto"):
@@ -196,6 +208,16 @@ def emit_vrr(em, la, lb, lc, ld, name, f_targets=None, policy="auto"):
     T = em.T
     L = la + lb + lc + ld
     ids = {n: k for k, n in enumerate(order)}
+    # nodes that another node reads; a target read by none is summed straight
+    # into its accumulator (acc + t1 + t2 ... contracts to multiply-adds)
+    used = set()
+    for n in order:
+        r = rec[n]
+        if r[0] != "base":
+            for p in r[1]:
+                for x in p:
+                    if isinstance(x, tuple) and len(x) == 3 and isinstance(x[0], tuple):
+                        used.add(x)
     acc_index = {}
     k = 0
     for e in e_t:
@@ -208,7 +230,6 @@ def emit_vrr(em, la, lb, lc, ld, name, f_targets=None, policy="auto"):
     em.lines.append(f"      {T} PAx, {T} PAy, {T} PAz, {T} WPx, {T} WPy, {T} WPz,")
     em.lines.append(f"      {T} QCx, {T} QCy, {T} QCz, {T} WQx, {T} WQy, {T} WQz,")
     em.lines.append(f"      {T} i2z, {T} roz, {T} i2e, {T} roe, {T} i2ze, {T}* __restrict__ acc) {{")
-    used = set()
     for n in order:
         r = rec[n]
         e, f, m = n
@@ -235,12 +256,17 @@ def emit_vrr(em, la, lb, lc, ld, name, f_targets=None, policy="auto"):
                 c = p[2]
                 coef = "i2ze" if c == 1 else f"({em.lit(c)} * i2ze)"
                 terms.append(f"{coef} * v{ids[p[3]]}")
+        if m == 0 and (e, f) in acc_index and n not in used:
+            k = acc_index[(e, f)]
+            em.lines.append(f"    acc[{k}] = acc[{k}] + " + " + ".join(terms) + ";")
+            continue
         em.lines.append(f"    const {T} {v} = " + " + ".join(terms) + ";")
         if m == 0 and (e, f) in acc_index:
             # accumulate a target as soon as it exists: its value dies here
             em.lines.append(f"    acc[{acc_index[(e, f)]}] += {v};")
     em.lines.append("  }")
-    return nacc, cost + nacc  # accumulation adds
+    flops = sum(_node_flops(rec[n]) for n in order)
+    return nacc, flops + nacc  # accumulation adds
 
 
 # --------------------------------------------------------- HRR + sph ----
