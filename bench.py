@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-jk", action="store_true", help="skip the Coulomb + exchange leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
+    ap.add_argument("--no-density", action="store_true", help="skip the density-screened leg")
     ap.add_argument("--batch-natom", type=str, default="6,20",
                     help="atom-count range of the batched systems (scaled-down config-3 recipe)")
     ap.add_argument("--serve-natom", type=str, default="6,24",
@@ -505,6 +506,28 @@ def main():
             "fp32_quartet_fraction": stm["quartets_fp32"] / max(1, stm["quartets"]),
             "max_abs_dK_vs_fp64_gpu": float(np.abs(Kmh - Kh).max()),
             "trPK_err_vs_fp64_gpu": float(abs(np.sum(Ph * Kmh) - np.sum(Ph * Kh))),
+        }
+    if not a.no_density:
+        # the same shard with the density-weighted test added to the Schwarz
+        # test (P of the workload is zero beyond 12 bohr and decays as
+        # exp(-r/3))
+        od = hfx.opts(tau=tau, omega=omega, density=True)
+        Kd = torch.empty_like(P)
+        hfx.build_K_shard(pairs, P, Kd, od, a.shard, a.shards)  # warm-up: |P| block maxima workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        std = hfx.build_K_shard(pairs, P, Kd, od, a.shard, a.shards, stats=True)
+        torch.cuda.synchronize()
+        td = time.perf_counter() - t0
+        print(f"# density-screened step: {td:.3f} s", file=sys.stderr, flush=True)
+        out["density_screened"] = {
+            "value": std["quartets"] / td,
+            "unit": "quartets/s",
+            "ms_per_step": 1e3 * td,
+            "quartets": std["quartets"],
+            "quartet_fraction_kept": std["quartets"] / max(1, q_per_step),
+            "speedup_vs_schwarz_only": ms / (1e3 * td),
+            "max_abs_dK_vs_schwarz_only": float(np.abs(Kd.cpu().numpy() - Kh).max()),
         }
     if not a.no_jk:
         # Coulomb J digested from the same quartets (FP64): cost over K alone

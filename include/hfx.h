@@ -82,8 +82,13 @@ typedef struct {
  * computed quartet, primitive quartets whose bound B_ab B_cd is below
  * prim_tau may be skipped, where B_ab is the Schwarz factor of the single
  * primitive pair (a bound on every primitive contribution); 0 keeps every
- * primitive quartet (exact evaluation of each computed quartet).  flags:
- * reserved, must be 0. */
+ * primitive quartet (exact evaluation of each computed quartet).  flags: 0,
+ * or HFX_FLAG_DENSITY_SCREEN: a quartet that passes the Schwarz test is
+ * computed only if also Q_IJ Q_KL D >= tau, where D is the largest |P|
+ * over the shell blocks its digestion multiplies -- (I,K) (I,L) (J,K) (J,L)
+ * for K, and (I,J) (K,L) as well when J is built (the density screening that
+ * Sec. 3 adds after the Schwarz test, read for Gaussian shells). */
+#define HFX_FLAG_DENSITY_SCREEN 1
 typedef struct {
     double tau;
     int32_t op;

@@ -19,6 +19,7 @@ HFX_OK, HFX_EINVAL, HFX_EUNSUPPORTED, HFX_ENOMEM, HFX_EBUSY, HFX_ENOTFOUND, HFX_
 STATUS_NAMES = ["OK", "EINVAL", "EUNSUPPORTED", "ENOMEM", "EBUSY", "ENOTFOUND", "EDEVICE", "EASYM"]
 OP_COULOMB, OP_ERFC = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
+FLAG_DENSITY_SCREEN = 1
 NCLASS = 21
 PAIR_CLASSES = ["ss", "ps", "pp", "ds", "dp", "dd"]
 CLASS_NAMES = [f"({PAIR_CLASSES[b]}|{PAIR_CLASSES[k]})" for b in range(6) for k in range(b + 1)]
@@ -118,14 +119,16 @@ PRIM_TAU_REL = 1e-6  # default primitive-quartet threshold relative to tau
 MIXED_CUT = 1e-7  # tuned: 1e-6 gives 1.7e-6 max |dK| on the 256-atom shard, 1e-5 gives ~2e-5
 
 
-def opts(tau=1e-10, omega=0.0, prec=PREC_FP64, mixed_cut=MIXED_CUT, op=None, prim_tau=None) -> Opts:
-    """Options; prim_tau defaults to 1e-6 tau (0 = every primitive quartet)."""
+def opts(tau=1e-10, omega=0.0, prec=PREC_FP64, mixed_cut=MIXED_CUT, op=None, prim_tau=None,
+         density=False) -> Opts:
+    """Options; prim_tau defaults to 1e-6 tau (0 = every primitive quartet);
+    density=True adds the density-weighted test to the Schwarz test."""
     if op is None:
         op = OP_ERFC if omega > 0 else OP_COULOMB
     if prim_tau is None:
         prim_tau = PRIM_TAU_REL * tau
     return Opts(tau=float(tau), op=int(op), omega=float(omega), prec=int(prec), mixed_cut=float(mixed_cut),
-                prim_tau=float(prim_tau), flags=0)
+                prim_tau=float(prim_tau), flags=FLAG_DENSITY_SCREEN if density else 0)
 
 
 def _stream_ptr(stream):

@@ -25,6 +25,8 @@ struct PairHdr {
     int32_t n;     // number of PrimRecs
     int32_t bfA;   // first spherical function of shell A
     int32_t bfB;   // first spherical function of shell B
+    int32_t shA;   // shell index of A
+    int32_t shB;   // shell index of B
     double ABx, ABy, ABz;
     int32_t diag;  // I == J
     int32_t id;    // global pair id
@@ -270,6 +272,12 @@ struct QuartetArgs {
     double mixed_cut;
     const double *bra_A;      // per bra slot
     const double *ket_gA;     // per ket group
+    // Density-weighted screening: 0 off; 1: a quartet of the range is
+    // computed only if also Q_p Q_q D >= tau, D the largest |P| over the shell
+    // blocks of its exchange digestion; 2: the Coulomb blocks count too.
+    int32_t dens;
+    int32_t nsh;              // shells (pmax is nsh x nsh)
+    const double *pmax;       // largest |P| of every shell block
     int32_t op;
     double om2;               // omega^2
     double prim_tau;          // primitive quartets with B_ab B_cd < prim_tau may be skipped
@@ -345,6 +353,55 @@ __device__ __forceinline__ int ket_cut(const QuartetArgs &a, int p, int g, int *
     return first_below(a.ket_Q, lo, hi, Qp, tlo);
 }
 
+// Density weight of the quartet (bra shells bA bB | ket pair k): the largest
+// |P| over the shell blocks its digestion multiplies (pmax is symmetric).
+__device__ __forceinline__ double dens_weight(const QuartetArgs &a, int bA, int bB, const PairHdr &k) {
+    const double *M = a.pmax;
+    const int64_t n = a.nsh;
+    double d = fmax(fmax(M[bA * n + k.shA], M[bA * n + k.shB]), fmax(M[bB * n + k.shA], M[bB * n + k.shB]));
+    if (a.dens == 2) d = fmax(d, fmax(M[bA * n + bB], M[k.shA * n + k.shB]));
+    return d;
+}
+
+// Calls body(q) once per tile of up to 64 ket slots of [lo, cut), q < 0 on
+// idle lanes.  With density screening the slots failing the density test are
+// dropped first: candidates are tested 64 at a time and the survivors queued
+// in LDS (wave ballot + prefix count), so every tile but the last is full.
+template <class Body>
+__device__ __forceinline__ void ket_tiles(const QuartetArgs &a, int p, const PairHdr &bh, int lo, int cut,
+                                          Body body) {
+    const int lane = threadIdx.x;
+    if (!a.dens) {
+        for (int q0 = lo; q0 < cut; q0 += 64) body(q0 + lane < cut ? q0 + lane : -1);
+        return;
+    }
+    __shared__ int queue[128];
+    const double Qp = a.bra_Q[p];
+    int nq = 0;
+    for (int c0 = lo; c0 < cut; c0 += 64) {
+        const int q = c0 + lane;
+        bool ok = false;
+        if (q < cut) {
+            const PairHdr kh = a.hdr[a.ket_ids[q]];
+            ok = Qp * a.ket_Q[q] * dens_weight(a, bh.shA, bh.shB, kh) >= a.tau;
+        }
+        const unsigned long long m = __ballot(ok);
+        if (ok) queue[nq + __popcll(m & ((1ull << lane) - 1ull))] = q;
+        nq += __popcll(m);
+        __syncthreads();
+        if (nq >= 64) {
+            const int qq = queue[lane];
+            const int rest = lane + 64 < nq ? queue[lane + 64] : 0;
+            __syncthreads();
+            if (lane + 64 < nq) queue[lane] = rest;
+            nq -= 64;
+            __syncthreads();
+            body(qq);
+        }
+    }
+    if (nq > 0) body(lane < nq ? queue[lane] : -1);
+}
+
 // One wave's work on one tile: 64 lanes walk the screened ket range of bra
 // pair p in ket group g; each lane holds slice W of one quartet's contracted
 // array, accumulated over all primitive quartets, and digests that slice's
@@ -367,10 +424,10 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
     const CPrimRec *brec = (const CPrimRec *)(a.prim + boff);
     const double bmax = brec->B;
     constexpr int NA = C::NACCP[W];
-    unsigned long long nprim = 0;
-    for (int q0 = lo; q0 < cut; q0 += 64) {
-        const int q = q0 + lane;
-        const bool act = q < cut;
+    unsigned long long nprim = 0, nquart = 0;
+    ket_tiles(a, p, bh, lo, cut, [&](int q) {
+        const bool act = q >= 0;
+        nquart += __popcll(__ballot(act));
         const int kid = a.ket_ids[act ? q : lo];
         const PairHdr kh = a.hdr[kid];
         double acc[NA];
@@ -405,8 +462,11 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
                 C::template digJ<W>(acc, x.ABx, x.ABy, x.ABz, y.ABx, y.ABy, y.ABz, x.bfA, x.bfB, y.bfA,
                                     y.bfB, deg, a.P, a.J, a.ld);
         }
+    });
+    if (W == 0 && a.count) {
+        if (lane == 0 && nquart) atomicAdd(&a.count[0], nquart);
+        if (nprim) atomicAdd(&a.count[1], nprim);
     }
-    if (W == 0 && a.count && nprim) atomicAdd(&a.count[1], nprim);
 }
 
 template <class C, int W, bool WJ = false, bool SWAP = false>
@@ -443,7 +503,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     const int lo2 = lo + sub * a.tq;
     const int cut2 = min(cut, lo2 + a.tq);
     if (cut2 <= lo2) return;
-    if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut2 - lo2));
     tile_dispatch<C, 0, WJ, SWAP>(a, w, p, g, lo2, cut2);
 }
 
@@ -461,10 +520,10 @@ __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, 
     const float bmax = brec->B;
     const float om2 = (float)a.om2, om = sqrtf(om2);
     constexpr int NA = C::NACCP[W];
-    unsigned long long nprim = 0;
-    for (int q0 = lo; q0 < cut; q0 += 64) {
-        const int q = q0 + lane;
-        const bool act = q < cut;
+    unsigned long long nprim = 0, nquart = 0;
+    ket_tiles(a, p, bh, lo, cut, [&](int q) {
+        const bool act = q >= 0;
+        nquart += __popcll(__ballot(act));
         const int kid = a.ket_ids[act ? q : lo];
         const PairHdr kh = a.hdr[kid];
         float acc[NA];
@@ -493,8 +552,11 @@ __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, 
                 C::template digJ<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB, kh.bfA,
                                     kh.bfB, deg, a.P, a.J, a.ld);
         }
+    });
+    if (W == 0 && a.count) {
+        if (lane == 0 && nquart) atomicAdd(&a.count[0], nquart);
+        if (nprim) atomicAdd(&a.count[1], nprim);
     }
-    if (W == 0 && a.count && nprim) atomicAdd(&a.count[1], nprim);
 }
 
 template <class C, int W, bool WJ = false>
@@ -525,7 +587,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     const int lo2 = lo + sub * a.tq;
     const int cut2 = min(cut, lo2 + a.tq);
     if (cut2 <= lo2) return;
-    if (w == 0 && threadIdx.x == 0 && a.count) atomicAdd(&a.count[0], (unsigned long long)(cut2 - lo2));
     tile_dispatch32<C, 0, WJ>(a, w, p, g, lo2, cut2);
 }
 
@@ -572,7 +633,6 @@ __device__ __forceinline__ void persist_loop(const BatchJob *__restrict__ jobs, 
             const int lo2 = lo + sub * J.tq;
             const int cut2 = min(cut, lo2 + J.tq);
             if (cut2 <= lo2) continue;
-            if (w == 0 && threadIdx.x == 0 && J.a.count) atomicAdd(&J.a.count[0], (unsigned long long)(cut2 - lo2));
             if constexpr (F32) tile_dispatch32<C, 0>(J.a, w, p, g, lo2, cut2);
             else tile_dispatch<C, 0, false, SWAP>(J.a, w, p, g, lo2, cut2);
         }

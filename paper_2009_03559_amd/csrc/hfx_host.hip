@@ -197,6 +197,18 @@ void launch_symmetrize(double *K, int64_t n, int64_t ld, hipStream_t st) {
     hipLaunchKernelGGL(k_symmetrize, dim3(g, g), dim3(16, 16), 0, st, K, n, ld);
 }
 
+// Largest |P_xy| of every shell block (X, Y): one thread per block.
+__global__ void k_pmax(const double *__restrict__ P, int64_t ld, const int32_t *__restrict__ bfo, int nsh,
+                       double *__restrict__ M) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nsh * nsh) return;
+    const int X = (int)(t / nsh), Y = (int)(t % nsh);
+    double m = 0.0;
+    for (int x = bfo[X]; x < bfo[X + 1]; ++x)
+        for (int y = bfo[Y]; y < bfo[Y + 1]; ++y) m = fmax(m, fabs(P[(int64_t)x * ld + y]));
+    M[t] = m;
+}
+
 // Per-block max |P_ij - P_ji| and max |P_ij|.
 __global__ void k_asym(const double *P, int64_t n, int64_t ld, double *part) {
     __shared__ double s0[256], s1[256];
@@ -325,7 +337,7 @@ hfx_status check_opts(const hfx_opts *o) {
     if (o->prec != HFX_PREC_FP64 && o->prec != HFX_PREC_MIXED) return fail(HFX_EINVAL, "unknown precision mode");
     if (o->prec == HFX_PREC_MIXED && !(o->mixed_cut >= 0.0)) return fail(HFX_EINVAL, "mixed_cut must be >= 0");
     if (!(o->prim_tau >= 0.0) || !std::isfinite(o->prim_tau)) return fail(HFX_EINVAL, "prim_tau must be finite and >= 0");
-    if (o->flags != 0) return fail(HFX_EINVAL, "flags are reserved and must be 0");
+    if (o->flags & ~HFX_FLAG_DENSITY_SCREEN) return fail(HFX_EINVAL, "unknown flag");
     return HFX_OK;
 }
 
@@ -420,6 +432,8 @@ extern "C" hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, co
             h.n = shells[a].nprim * shells[b].nprim;
             h.bfA = P->bfo[a];
             h.bfB = P->bfo[b];
+            h.shA = a;
+            h.shB = b;
             const double *A = xyz + 3 * shells[a].atom, *B = xyz + 3 * shells[b].atom;
             h.ABx = A[0] - B[0];
             h.ABy = A[1] - B[1];
@@ -480,6 +494,7 @@ extern "C" hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, co
     ALLOC(P->d_part, 2 * PCHECK_BLOCKS * sizeof(double));
     ALLOC(P->d_count, NCOUNT * sizeof(unsigned long long));
     ALLOC(P->d_class_ids, npair * sizeof(int32_t));
+    ALLOC(P->d_bfo, (nshell + 1) * sizeof(int32_t));
     ALLOC_TMP(d_shA, npair * sizeof(int32_t));
     ALLOC_TMP(d_shB, npair * sizeof(int32_t));
     ALLOC_TMP(d_sh, nshell * sizeof(ShellDev));
@@ -507,6 +522,8 @@ extern "C" hfx_status hfx_build_shell_pairs(const double *xyz, int32_t natom, co
         for (int c = 0; c < 6; ++c) ids.insert(ids.end(), P->class_ids[c].begin(), P->class_ids[c].end());
         if (e == hipSuccess)
             e = hipMemcpyAsync(P->d_class_ids, ids.data(), npair * sizeof(int32_t), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P->d_bfo, P->bfo.data(), (nshell + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host vector dies here
     }
     if (e == hipSuccess) {
@@ -537,6 +554,8 @@ hfx_pairs_s::~hfx_pairs_s() {
     hipFree(d_count);
     hipFree(d_part);
     hipFree(d_class_ids);
+    hipFree(d_bfo);
+    hipFree(d_pmax);
     for (auto &e : ev)
         if (e) hipEventDestroy(e);
 }
@@ -728,6 +747,41 @@ hfx_status check_P(const double *P, int64_t n, int64_t ld, hipStream_t st, doubl
     return HFX_OK;
 }
 
+// Shell-block maxima of |P| for density screening (per build: P changes
+// between calls).  The nshell^2 array is allocated on the handle's first
+// density-screened build; may_allocate = false refuses to make it.
+hfx_status shell_pmax(hfx_pairs p, const double *P, int64_t ld, bool may_allocate, hipStream_t st) {
+    const int64_t n2 = (int64_t)p->nshell * p->nshell;
+    if (!p->d_pmax) {
+        if (!may_allocate)
+            return fail(HFX_EINVAL, "density-screening workspace is not resident in the handle "
+                                    "(run hfx_build_K once with the same options first)");
+        if (hipMalloc(&p->d_pmax, n2 * sizeof(double)) != hipSuccess)
+            return fail(HFX_ENOMEM, "device allocation of the |P| block maxima failed");
+        p->dev_bytes += n2 * sizeof(double);
+    }
+    hipLaunchKernelGGL(k_pmax, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, P, ld, p->d_bfo, p->nshell,
+                       p->d_pmax);
+    HIPCHK(hipGetLastError());
+    return HFX_OK;
+}
+
+int density_mode(const hfx_opts *o, bool coulomb) {
+    return (o->flags & HFX_FLAG_DENSITY_SCREEN) ? (coulomb ? 2 : 1) : 0;
+}
+
+// Ket candidates per block under density screening: longer than the plain
+// blocks so that the survivors fill whole 64-lane tiles.  HFX_TQ_DENS
+// overrides it (tuning).
+static int quartet_block_dens() {
+    static int env = -1;
+    if (env < 0) {
+        const char *e = std::getenv("HFX_TQ_DENS");
+        env = (e && *e) ? std::max(64, std::atoi(e)) : 0;
+    }
+    return env > 0 ? env : 512;
+}
+
 const double *model_vrr();
 const double *model_post();
 double model_prim_overhead(int op, int L);
@@ -776,7 +830,10 @@ hfx_status launch_classes(hfx_pairs p, const double *P, double *K, double *J, in
             const int L = PAIR_L[cb][0] + PAIR_L[cb][1] + PAIR_L[ck][0] + PAIR_L[ck][1];
             int gmax = 1;
             for (size_t gi = 0; gi + 1 < Kl.goff.size(); ++gi) gmax = std::max(gmax, Kl.goff[gi + 1] - Kl.goff[gi]);
-            a.tq = quartet_block(L);
+            a.dens = density_mode(o, J != nullptr);
+            a.nsh = p->nshell;
+            a.pmax = p->d_pmax;
+            a.tq = a.dens ? quartet_block_dens() : quartet_block(L);
             a.nsub = (gmax + a.tq - 1) / a.tq;
             const int64_t nblk = (int64_t)((B.n - shard + nshards - 1) / nshards) * Kl.ngrp * a.nsub;
             if (nblk > (int64_t)UINT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
@@ -853,6 +910,10 @@ hfx_status hfx::build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, in
     }
     s = check_P(P_dev, n, ld, st, ws.part);
     if (s != HFX_OK) return s;
+    if (o->flags & HFX_FLAG_DENSITY_SCREEN) {
+        s = shell_pmax(p, P_dev, ld, ws_in == nullptr, st);
+        if (s != HFX_OK) return s;
+    }
     if (!ws_in) {
         s = compute_bounds(p, o, st);
         if (s != HFX_OK) return s;

@@ -51,6 +51,8 @@ hfx_status build_K_impl(hfx_pairs p, const double *P_dev, double *K_dev, int64_t
 void launch_fill_K(double *K, int64_t n, int64_t ld, hipStream_t st);
 void launch_fill_u64(unsigned long long *c, int n, hipStream_t st);
 void launch_symmetrize(double *K, int64_t n, int64_t ld, hipStream_t st);
+hfx_status shell_pmax(hfx_pairs p, const double *P, int64_t ld, bool may_allocate, hipStream_t st);
+int density_mode(const hfx_opts *o, bool coulomb);
 const double *model_vrr();
 const double *model_post();
 double model_prim_overhead(int op, int L);
@@ -81,6 +83,8 @@ struct hfx_pairs_s {
     unsigned long long *d_count = nullptr;  // workspace of builds on this handle
     double *d_part = nullptr;
     int32_t *d_class_ids = nullptr;         // pair ids of every pair class, concatenated
+    int32_t *d_bfo = nullptr;               // first function of every shell (nshell + 1)
+    double *d_pmax = nullptr;               // largest |P| of every shell block (density screening)
     hipEvent_t ev[HFX_NCLASS + 1] = {};      // class-kernel timing events
     bool have_Q = false;
     int q_op = -1;

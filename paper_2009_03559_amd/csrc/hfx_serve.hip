@@ -198,6 +198,9 @@ static void make_jobs(ClassJobs &cj, int ci, int nsys, hfx_pairs const *p, const
         a.mixed_cut = o->mixed_cut;
         a.bra_A = B.d_A;
         a.ket_gA = Kl.d_gA;
+        a.dens = density_mode(o, false);
+        a.nsh = p[s]->nshell;
+        a.pmax = p[s]->d_pmax;
         a.count = cnt ? cnt[s] + 4 * ci + (f32 ? 2 : 0) : nullptr;
         int gmax = 1;
         for (size_t g = 0; g + 1 < Kl.goff.size(); ++g) gmax = std::max(gmax, Kl.goff[g + 1] - Kl.goff[g]);
@@ -301,6 +304,8 @@ hfx_status batch_impl(int32_t nsys, const hfx_pairs *p, const double *const *P, 
         s = compute_bounds(p[i], o, st);
         if (s != HFX_OK) return s;
         s = build_lists(p[i], o->tau, o->prec == HFX_PREC_MIXED, st);
+        if (s != HFX_OK) return s;
+        if (o->flags & HFX_FLAG_DENSITY_SCREEN) s = shell_pmax(p[i], P[i], ld[i], true, st);
         if (s != HFX_OK) return s;
         if (o->prec == HFX_PREC_MIXED) {
             s = ensure_prim32(p[i], st);

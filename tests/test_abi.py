@@ -73,11 +73,16 @@ def test_too_many_functions_rejected_on_host():
     (dict(omega=-0.1, op=hfx.OP_ERFC), hfx.HFX_EINVAL),
     (dict(prec=7), hfx.HFX_EINVAL),
     (dict(prim_tau=-1.0), hfx.HFX_EINVAL),
+    (dict(flags=6), hfx.HFX_EINVAL),
 ])
 def test_invalid_options_rejected_on_host(kw, status):
     s = hi.config0()
+    flags = kw.pop("flags", None)
+    o = hfx.opts(**kw)
+    if flags is not None:
+        o.flags = flags
     with pytest.raises(hfx.HfxError) as e:
-        hfx.build_shell_pairs(*_sys_args(s), o=hfx.opts(**kw), stream=0)
+        hfx.build_shell_pairs(*_sys_args(s), o=o, stream=0)
     assert e.value.status == status
 
 
