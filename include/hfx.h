@@ -231,6 +231,24 @@ int64_t hfx_pairs_device_bytes(hfx_pairs p);
 hfx_status hfx_eval_quartets(hfx_pairs p, const hfx_opts *o, int64_t n, const int32_t *quartets,
                              double *out, void *stream);
 
+/* Exchange build that allocates no device memory: for callers that cannot
+ * allocate (code under HIP stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, result and errors as hfx_build_K
+ * (same kernels), with two differences.  (1) Nothing is built on demand: the
+ * handle must already hold the Schwarz bounds for this kernel and omega, the
+ * screening lists for this tau, in mixed precision the FP32 records and with
+ * density screening the array of |P| block maxima -- one hfx_build_K with the
+ * same options on the handle leaves them resident; otherwise EINVAL, with
+ * nothing allocated.  (2) Its workspace (the P
+ * symmetry check's partial maxima and the quartet counters) is a fixed
+ * static device array of HFX_NOALLOC_SCRATCH_BYTES per GPU, independent of
+ * the system size, held until the process ends and shared by every call on
+ * that GPU: calls that overlap in time on one GPU race on it.  Synchronises
+ * the stream (the symmetry check of P). */
+#define HFX_NOALLOC_SCRATCH_BYTES 17152
+hfx_status hfx_build_K_noalloc(hfx_pairs p, const double *P_dev, double *K_dev, int64_t ld,
+                               const hfx_opts *o, void *stream, hfx_stats *st_or_null);
+
 void hfx_pairs_destroy(hfx_pairs p);
 void hfx_server_destroy(hfx_server s);
 const char *hfx_last_error(void);

@@ -62,7 +62,7 @@ def build(jobs: int | None = None, verbose: bool = True, only_changed: bool = Fa
     subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_eri.py"), "--outdir", GEN,
                            "--model", os.path.join(GEN, "model.json")])
     srcs = sorted(os.path.join(GEN, f) for f in os.listdir(GEN) if f.endswith(".hip"))
-    srcs += [os.path.join(CSRC, f) for f in ("hfx_host.hip", "hfx_serve.hip")]
+    srcs += [os.path.join(CSRC, f) for f in ("hfx_host.hip", "hfx_serve.hip", "hfx_noalloc.hip")]
     # largest classes first so the pool finishes together (a class's
     # Coulomb-digesting variant shares its header)
     srcs.sort(key=lambda s: -os.path.getsize(_header_of(s)) if os.path.exists(_header_of(s)) else 0)
