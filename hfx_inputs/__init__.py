@@ -34,6 +34,7 @@ __all__ = [
     "config3",
     "served_requests",
     "si64_like",
+    "periodic_cluster",
     "OMEGA_HSE",
 ]
 
@@ -256,6 +257,75 @@ def perturbed_density(P0: np.ndarray, rng, rel: float = 1e-3) -> np.ndarray:
     E = rng.standard_normal(P0.shape)
     E = np.triu(E) + np.triu(E, 1).T
     return P0 * (1.0 + rel * E)
+
+
+def periodic_cluster(natom_cell: int = 2, cell_len: float = 5.0, reach=(1, 1, 1), seed: int = 6,
+                     lmax: int = 2, nprim_range=(1, 2), alpha_range=(0.3, 8.0), p_cut: float = 9.0,
+                     p_decay: float = 2.0) -> System:
+    """A periodic crystal (simple-cubic cell of side cell_len bohr holding
+    natom_cell atoms, jittered lattice sites of the cell) written as a finite
+    cluster of image cells n in [-reach, reach] (per axis), home cell first:
+    atoms, shells and functions of cell (0, 0, 0) come first, then the other
+    cells in lexicographic order of n.  Shells per atom as lattice_system
+    (2s+2p+1d, or 2s+2p for lmax 1), identical in every image.
+
+    The density matrix is periodic and Hermitian: P^R_{nu sigma} between
+    nu of cell 0 and sigma of cell R is u * exp(-r/p_decay), zero beyond
+    p_cut, with r the distance of the two functions' atoms and u uniform in
+    [-1, 1] drawn once per (R, nu, sigma) with u(R, nu, sigma) = u(-R, sigma, nu).
+    The cluster's P is P_big[(N, nu)][(H, sigma)] = P^{H-N}_{nu sigma}.
+    meta: nhome_shell, ncell, cells (integer offsets in cluster order),
+    nf_cell (functions per cell)."""
+    rng = np.random.default_rng(seed)
+    m = int(math.ceil(natom_cell ** (1.0 / 3.0) - 1e-12))
+    sub = cell_len / max(m, 1)
+    sites = [(i, j, k) for k in range(m) for j in range(m) for i in range(m)][:natom_cell]
+    cell_xyz = (np.array(sites, dtype=np.float64) + 0.5) * sub + rng.uniform(-0.3, 0.3, size=(natom_cell, 3))
+    ls = [0, 0, 1, 1] + ([2] if lmax >= 2 else [])
+    cell_shells = []
+    for a in range(natom_cell):
+        for l in ls:
+            npr = int(rng.integers(nprim_range[0], nprim_range[1] + 1))
+            e = np.sort(_log_uniform(rng, alpha_range[0], alpha_range[1], npr))[::-1].copy()
+            c = rng.uniform(0.1, 1.0, size=npr)
+            cell_shells.append((a, l, e, c))
+    rx, ry, rz = reach
+    cells = [(0, 0, 0)] + [(i, j, k) for i in range(-rx, rx + 1) for j in range(-ry, ry + 1)
+                           for k in range(-rz, rz + 1) if (i, j, k) != (0, 0, 0)]
+    xyz, shells = [], []
+    for ci, n in enumerate(cells):
+        shift = cell_len * np.array(n, dtype=np.float64)
+        xyz.extend(cell_xyz + shift)
+        for (a, l, e, c) in cell_shells:
+            shells.append((ci * natom_cell + a, l, e, c))
+    xyz = np.array(xyz)
+    nf = sum(2 * sh[1] + 1 for sh in cell_shells)
+    f_atom = np.repeat([sh[0] for sh in cell_shells], [2 * sh[1] + 1 for sh in cell_shells])
+    # u per cell difference R in [-2 reach, 2 reach], Hermitian: u(R) = u(-R)^T
+    span = [2 * r for r in reach]
+    diffs = [(i, j, k) for i in range(-span[0], span[0] + 1) for j in range(-span[1], span[1] + 1)
+             for k in range(-span[2], span[2] + 1)]
+    U = {R: rng.uniform(-1.0, 1.0, size=(nf, nf)) for R in diffs}
+    PR = {}
+    for R in diffs:
+        mR = tuple(-x for x in R)
+        u = 0.5 * (U[R] + U[mR].T)
+        shift = cell_len * np.array(R, dtype=np.float64)
+        d = np.linalg.norm(cell_xyz[f_atom][:, None, :] - (cell_xyz[f_atom][None, :, :] + shift), axis=-1)
+        P = u * np.exp(-d / p_decay)
+        P[d > p_cut] = 0.0
+        PR[R] = P
+    nc = len(cells)
+    Pbig = np.zeros((nc * nf, nc * nf))
+    for a, Na in enumerate(cells):
+        for b, Hb in enumerate(cells):
+            R = tuple(h - n_ for h, n_ in zip(Hb, Na))
+            Pbig[a * nf:(a + 1) * nf, b * nf:(b + 1) * nf] = PR[R]
+    Pbig = 0.5 * (Pbig + Pbig.T)  # exact symmetry (already Hermitian up to rounding)
+    sysm = _pack(xyz, shells, Pbig, dict(name="periodic_cluster", seed=seed, natom_cell=natom_cell,
+                                           cell_len=cell_len, reach=tuple(reach)))
+    sysm.meta.update(nhome_shell=len(cell_shells), ncell=nc, cells=cells, nf_cell=nf)
+    return sysm
 
 
 def si64_like(basis: str = "SZ", seed: int = 5) -> System:

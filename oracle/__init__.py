@@ -61,6 +61,9 @@ def lib():
         L.oracle_build_JK_density.restype = ctypes.c_int
         L.oracle_build_JK_density.argtypes = basis + [_f64p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                                       ctypes.c_void_p, _f64p, _f64p, _i64p]
+        L.oracle_build_K_periodic.restype = ctypes.c_int
+        L.oracle_build_K_periodic.argtypes = basis + [ctypes.c_int, _f64p, ctypes.c_double, ctypes.c_double,
+                                                      ctypes.c_int, _f64p, _i64p]
         L.oracle_digest_list.restype = ctypes.c_int
         L.oracle_digest_list.argtypes = basis + [_f64p, ctypes.c_double, ctypes.c_int64, _i64p,
                                                  ctypes.c_int, _f64p]
@@ -183,6 +186,23 @@ def build_K_density(sys, tau=1e-10, omega=0.0, nthreads=0, P=None, coulomb=False
         raise ValueError("oracle_build_JK_density: invalid basis")
     c = dict(quartets=int(cnt[0]), prim_quartets=int(cnt[1]), per_class=cnt[2:].copy())
     return (J, K, Q[:npair], c) if coulomb else (K, Q[:npair], c)
+
+
+def build_K_periodic(cl, tau=1e-10, omega=0.0, nthreads=0):
+    """Periodic exchange of a cluster laid out home cell first
+    (cl.meta['nhome_shell'] shells): returns (Kout, counts) with Kout the rows
+    of the home cell's functions, Kout[mu][b] = K^{cell(b)}_{mu f(b)}."""
+    nhome = int(cl.meta["nhome_shell"])
+    n = cl.nbf
+    nh = int(np.sum(2 * cl.shell_l[:nhome] + 1))
+    P = np.ascontiguousarray(cl.P, dtype=np.float64)
+    K = np.zeros((nh, n), dtype=np.float64)
+    cnt = np.zeros(23, dtype=np.int64)
+    rc = lib().oracle_build_K_periodic(*_basis_args(cl), nhome, P.ravel(), float(tau), float(omega), int(nthreads),
+                                       K.ravel(), cnt)
+    if rc:
+        raise ValueError("oracle_build_K_periodic: invalid basis")
+    return K, dict(quartets=int(cnt[0]), prim_quartets=int(cnt[1]), per_class=cnt[2:].copy())
 
 
 def digest_list(sys, pairs_pq: np.ndarray, omega=0.0, nthreads=0, P=None) -> np.ndarray:

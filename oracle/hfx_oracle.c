@@ -736,3 +736,87 @@ int oracle_digest_list(const double *xyz, int nshell, const int32_t *atom, const
     free(bfo); free(cn);
     return 0;
 }
+
+
+/* ------------------------------------------------------------------------- */
+/* Periodic exchange (Sec. 2, eq. V^X without its -1/2):
+ *     K^G_{mu lambda} = sum_{nu, sigma} sum_{N, H} (mu^0 nu^N | lambda^G sigma^H) P^{H-N}_{nu sigma},
+ * mu in the home cell, the lattice sums over N, H (and the output cells G)
+ * truncated to the cells of a finite cluster.  The caller lays the cluster
+ * out as one basis: the home cell's shells first (shells 0 .. nhome-1), then
+ * the image shells; Pbig[a][b] = P^{cell(b)-cell(a)}_{f(a) f(b)} (n x n over the
+ * cluster's functions) and Kout[mu][b] = K^{cell(b)}_{mu f(b)} (rows: the home
+ * cell's functions, the first ones of the basis; n columns).  In cluster terms
+ * Kout[i][k] = sum_{j,l} (ij|kl) Pbig[j][l] for i in the home cell.
+ * Screening: the shell quartet (IJ|KL) is evaluated iff Q_IJ Q_KL >= tau, with
+ * the cluster's Schwarz factors.  Plain loops over ordered shell quartets
+ * with I in the home cell; no permutational symmetry is used.
+ * counts[0] = the screened combinations (unordered pair {I,J} with I or J in
+ * the home cell, unordered pair {K,L}); counts[1] = their primitive quartets;
+ * counts[2 + c] = per class (oracle_class_index).                           */
+int oracle_build_K_periodic(const double *xyz, int nshell, const int32_t *atom, const int32_t *l,
+                            const int32_t *nprim, const int32_t *off, const double *exps,
+                            const double *coefs, int nhome, const double *Pbig, double tau, double omega,
+                            int nthreads, double *Kout, int64_t *counts) {
+    basis_t B; double *cn;
+    if (nhome < 0 || nhome > nshell) return 1;
+    if (setup_basis(&B, xyz, nshell, atom, l, nprim, off, exps, coefs, &cn)) return 1;
+    int *bfo = malloc(sizeof(int) * (nshell + 1));
+    bfo[0] = 0;
+    for (int s = 0; s < nshell; s++) bfo[s + 1] = bfo[s] + nsph(l[s]);
+    int64_t n = bfo[nshell], nh = bfo[nhome];
+    int64_t npair = (int64_t)nshell * (nshell + 1) / 2;
+    double *Q = malloc(sizeof(double) * (npair > 0 ? npair : 1));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    oracle_schwarz(xyz, nshell, atom, l, nprim, off, exps, coefs, omega, Q);
+    memset(Kout, 0, sizeof(double) * nh * n);
+    #pragma omp parallel
+    {
+        vtab_t *W = malloc(sizeof(vtab_t));
+        double *Kp = calloc((size_t)(nh * n), sizeof(double));
+        double blk[625];
+        #pragma omp for schedule(dynamic, 1) collapse(2)
+        for (int I = 0; I < nhome; I++)
+        for (int J = 0; J < nshell; J++) {
+            int64_t pij = I >= J ? (int64_t)I * (I + 1) / 2 + J : (int64_t)J * (J + 1) / 2 + I;
+            for (int K = 0; K < nshell; K++)
+            for (int L = 0; L < nshell; L++) {
+                int64_t pkl = K >= L ? (int64_t)K * (K + 1) / 2 + L : (int64_t)L * (L + 1) / 2 + K;
+                if (!(Q[pij] * Q[pkl] >= tau)) continue;
+                shell_quartet(&B, I, J, K, L, omega, W, blk);
+                int ni = nsph(l[I]), nj = nsph(l[J]), nk = nsph(l[K]), nl = nsph(l[L]);
+                for (int i = 0; i < ni; i++)
+                for (int j = 0; j < nj; j++)
+                for (int k = 0; k < nk; k++)
+                for (int q = 0; q < nl; q++) {
+                    double v = blk[((i * nj + j) * nk + k) * nl + q];
+                    Kp[(int64_t)(bfo[I] + i) * n + bfo[K] + k] += v * Pbig[(int64_t)(bfo[J] + j) * n + bfo[L] + q];
+                }
+            }
+        }
+        #pragma omp critical
+        for (int64_t x = 0; x < nh * n; x++) Kout[x] += Kp[x];
+        free(Kp); free(W);
+    }
+    if (counts) {
+        int64_t cnt[2 + 21] = {0};
+        for (int I = 0; I < nshell; I++)
+        for (int J = 0; J <= I; J++) {
+            if (!(I < nhome || J < nhome)) continue;
+            int64_t pij = (int64_t)I * (I + 1) / 2 + J;
+            for (int K = 0; K < nshell; K++)
+            for (int L = 0; L <= K; L++) {
+                int64_t pkl = (int64_t)K * (K + 1) / 2 + L;
+                if (!(Q[pij] * Q[pkl] >= tau)) continue;
+                cnt[0]++;
+                cnt[1] += (int64_t)nprim[I] * nprim[J] * nprim[K] * nprim[L];
+                cnt[2 + oracle_class_index(l[I], l[J], l[K], l[L])]++;
+            }
+        }
+        memcpy(counts, cnt, sizeof(cnt));
+    }
+    free(Q); free(bfo); free(cn);
+    return 0;
+}

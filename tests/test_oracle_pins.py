@@ -788,3 +788,56 @@ def test_density_screening_tau_zero_keeps_everything():
     Kd, _, cd = oracle.build_K_density(s, tau=0.0, omega=0.11)
     assert cd["quartets"] == c0["quartets"] == 136 * 137 // 2
     assert np.abs(Kd - K0).max() <= 1e-14 * np.abs(K0).max()
+
+
+# ------------------------------------------- periodic exchange (next row) ----
+def test_periodic_home_cell_only_is_the_molecular_build():
+    """A cluster of the home cell alone: the periodic sum is the molecular
+    exchange matrix (every row, every column)."""
+    cl = hi.periodic_cluster(natom_cell=3, reach=(0, 0, 0), lmax=2, nprim_range=(1, 3))
+    assert cl.meta["nhome_shell"] == cl.nshell
+    Kp, cnt = oracle.build_K_periodic(cl, tau=1e-10, omega=0.11)
+    Km, Q, cm = oracle.build_K(cl, tau=1e-10, omega=0.11)
+    assert Kp.shape == Km.shape
+    assert np.abs(Kp - Km).max() <= 1e-13 * np.abs(Km).max()
+    # combinations of two (unordered) pairs in either order: twice the unique
+    # quartets less the diagonal ones
+    assert cnt["quartets"] == 2 * cm["quartets"] - int((Q * Q >= 1e-10).sum())
+
+
+def test_periodic_equals_brute_force_tensor_and_cluster_rows():
+    """tau = 0 over a three-cell chain: K^G_{mu lambda} = sum_{j,l} (mu j|lambda l)
+    Pbig[j][l] from the n^4 ERI tensor of the whole cluster, and the home-cell
+    rows of the molecular build of the cluster (itself pinned to the tensor)."""
+    cl = hi.periodic_cluster(natom_cell=1, reach=(1, 0, 0), lmax=1, nprim_range=(1, 2))
+    nh = int(np.sum(2 * cl.shell_l[:cl.meta["nhome_shell"]] + 1))
+    Kp, cnt = oracle.build_K_periodic(cl, tau=0.0, omega=0.11)
+    G = oracle.eri_tensor(cl, omega=0.11)
+    Kb = np.einsum("ijkl,jl->ik", G[:nh], cl.P)
+    assert np.abs(Kp - Kb).max() <= 1e-13 * np.abs(Kb).max()
+    Km, _, _ = oracle.build_K(cl, tau=0.0, omega=0.11)
+    assert np.abs(Kp - Km[:nh]).max() <= 1e-13 * np.abs(Km).max()
+    npair = cl.nshell * (cl.nshell + 1) // 2
+    nhs = cl.meta["nhome_shell"]
+    home_pairs = sum(1 for I in range(cl.nshell) for J in range(I + 1) if I < nhs or J < nhs)
+    assert cnt["quartets"] == home_pairs * npair
+
+
+def test_periodic_counts_and_screening_bound():
+    """27 cells: the screened combinations equal a direct count from the
+    Schwarz factors, and the screened K differs from the tau = 0 K by at most
+    what the dropped quartets can contribute."""
+    cl = hi.periodic_cluster(natom_cell=1, reach=(1, 1, 1), lmax=1, nprim_range=(1, 2))
+    tau = 1e-6
+    Kp, cnt = oracle.build_K_periodic(cl, tau=tau, omega=0.11)
+    K0, _ = oracle.build_K_periodic(cl, tau=0.0, omega=0.11)
+    Q = oracle.schwarz(cl, omega=0.11)
+    nhs = cl.meta["nhome_shell"]
+    pid = [(I, J) for I in range(cl.nshell) for J in range(I + 1)]
+    home = np.array([I < nhs or J < nhs for (I, J) in pid])
+    qq = np.outer(Q[home], Q)
+    assert cnt["quartets"] == int((qq >= tau).sum())
+    # each dropped (ordered) shell quartet adds at most Q_IJ Q_KL max|P| per
+    # function pair, <= 3 x 3 functions for s/p shells, both ket orders
+    bound = 2 * 9 * np.abs(cl.P).max() * qq[qq < tau].sum() * 2
+    assert 0 < np.abs(Kp - K0).max() <= bound
