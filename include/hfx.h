@@ -182,6 +182,26 @@ hfx_status hfx_build_JK_shard(hfx_pairs p, const double *P_dev, double *J_dev, d
                               const hfx_opts *o, int32_t shard, int32_t nshards, void *stream,
                               hfx_stats *st_or_null);
 
+/* Periodic exchange (Sec. 2, eq. V^X without its -1/2): for a crystal
+ * written as a finite cluster of image cells,
+ *     K^G_{mu lambda} = sum_{nu sigma} sum_{N H} (mu^0 nu^N | lambda^G sigma^H) P^{H-N}_{nu sigma}
+ * with mu in the home cell (the paper's list-IJ: first index in the unit
+ * cell) and nu, sigma, lambda over every cell of the cluster (list-KL over
+ * the supercell); the lattice sums run over the cluster's cells and are
+ * screened by Q_IJ Q_KL >= tau.  p: pair handle of the cluster, whose first
+ * nhome_shell shells (and functions) are the home cell's.  P_dev: device,
+ * n_bf x n_bf (leading dimension ldP), P_big[a][b] = P^{cell(b)-cell(a)}_{f(a)
+ * f(b)} -- symmetric.  K_dev: device, n_home x n_bf (leading dimension ldK,
+ * n_home = functions of the home cell), overwritten: K_dev[mu][b] =
+ * K^{cell(b)}_{mu f(b)}.  Every combination of a kept pair with a home-cell
+ * shell and a kept pair of the cluster is evaluated (the ket pair's two
+ * orders digested together), FP64 only.  Synchronises the stream.  Errors:
+ * as hfx_build_K; EINVAL (nhome_shell not in [1, nshell], ldP or ldK <
+ * n_bf, aliasing), EUNSUPPORTED (mixed precision or flags). */
+hfx_status hfx_build_K_periodic(hfx_pairs p, int32_t nhome_shell, const double *P_dev, int64_t ldP,
+                                double *K_dev, int64_t ldK, const hfx_opts *o, void *stream,
+                                hfx_stats *st_or_null);
+
 /* Many independent systems in one persistent launch per pass, fed by a
  * device work queue (Sec. 5 proposes dynamic distribution of the quartet
  * work; here the queue is shared by all systems).  Arrays of length nsys;

@@ -31,7 +31,8 @@ EXPORTS = ["hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_bu
            "hfx_build_K_shard",
            "hfx_build_K_batch",
            "hfx_server_create", "hfx_submit", "hfx_poll", "hfx_pairs_nbf", "hfx_pairs_npair",
-           "hfx_pairs_device_bytes", "hfx_eval_quartets", "hfx_build_K_noalloc", "hfx_pairs_destroy",
+           "hfx_pairs_device_bytes", "hfx_eval_quartets", "hfx_build_K_noalloc", "hfx_build_K_periodic",
+           "hfx_pairs_destroy",
            "hfx_server_destroy", "hfx_last_error"]
 
 
@@ -88,6 +89,8 @@ def lib():
                                         ctypes.c_int32, vp, ctypes.POINTER(Stats)]
         L.hfx_build_K_noalloc.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(Opts), vp,
                                           ctypes.POINTER(Stats)]
+        L.hfx_build_K_periodic.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.c_int64,
+                                           ctypes.POINTER(Opts), vp, ctypes.POINTER(Stats)]
         L.hfx_build_K_batch.argtypes = [ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp,
                                         ctypes.POINTER(Stats)]
         L.hfx_server_create.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(vp)]
@@ -102,7 +105,7 @@ def lib():
         L.hfx_server_destroy.argtypes = [vp]
         L.hfx_server_destroy.restype = None
         for f in ("hfx_build_shell_pairs", "hfx_schwarz_bounds", "hfx_build_K", "hfx_build_JK", "hfx_build_JK_shard",
-                  "hfx_build_K_shard", "hfx_build_K_noalloc",
+                  "hfx_build_K_shard", "hfx_build_K_noalloc", "hfx_build_K_periodic",
                   "hfx_build_K_batch",
                   "hfx_server_create", "hfx_submit", "hfx_poll", "hfx_eval_quartets"):
             getattr(L, f).restype = ctypes.c_int
@@ -215,6 +218,16 @@ def build_K_noalloc(p: Pairs, P, K, o: Opts, stream=None, stats=False):
     st = Stats() if stats else None
     _check(lib().hfx_build_K_noalloc(p.handle, _ptr(P), _ptr(K), ld, ctypes.byref(o), _stream_ptr(stream),
                                      ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def build_K_periodic(p: Pairs, nhome_shell: int, P, K, o: Opts, stream=None, stats=False):
+    """Periodic exchange of a cluster laid out home cell first: P (n x n,
+    P_big) and K (n_home x n) device tensors; K[mu][b] = K^{cell(b)}_{mu f(b)}."""
+    st = Stats() if stats else None
+    _check(lib().hfx_build_K_periodic(p.handle, int(nhome_shell), _ptr(P), int(P.stride(0)), _ptr(K),
+                                      int(K.stride(0)), ctypes.byref(o), _stream_ptr(stream),
+                                      ctypes.byref(st) if st is not None else None))
     return st.as_dict() if st is not None else None
 
 

@@ -30,7 +30,7 @@ COMMON_HEADERS = [os.path.join(CSRC, "hfx_device.hpp"), os.path.join(CSRC, "hfx_
 
 
 def _header_of(src: str) -> str:
-    return src.replace("tu_", "eri_").replace("_jk.hip", ".hip").replace(".hip", ".h")
+    return src.replace("tu_", "eri_").replace("_jk.hip", ".hip").replace("_per.hip", ".hip").replace(".hip", ".h")
 
 
 def _stale(src: str) -> bool:

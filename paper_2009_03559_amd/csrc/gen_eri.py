@@ -374,6 +374,11 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
 
     mode "K": exchange (below).  mode "J": the Coulomb digestion of the same
     shares, J'_ab += 2 d v P_cd and J'_cd += 2 d v P_ab (J = J' + J'^T).
+    mode "R": exchange rows chosen per call (periodic builds): the four sums
+    of mode "K" are added with weights wA, wB to rows of A and B and, P being
+    symmetric, the same sums with weights wC, wD to rows of C and D
+    (K_ca += wC v P_db = wC v P_bd, ...); P and K have their own leading
+    dimensions and no K' + K'^T follows.
 
     acc holds [e|f] for every bra e (la..la+lb) and the ket components f in
     `f_part` (layout e-major).  The bra horizontal recurrence and spherical
@@ -403,6 +408,10 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
         # original index order)
         L.append(f"      {T} ABx, {T} ABy, {T} ABz, {T} CDx, {T} CDy, {T} CDz, int64_t sab, int64_t scd,")
         L.append("      double* __restrict__ out) {")
+    elif mode == "R":
+        L.append(f"      {T} ABx, {T} ABy, {T} ABz, {T} CDx, {T} CDy, {T} CDz, int a0, int b0, int c0, int d0,")
+        L.append("      double wA, double wB, double wC, double wD, const double* __restrict__ P, int64_t ldP,")
+        L.append("      double* K, int64_t ldK) {")
     else:
         L.append(f"      {T} ABx, {T} ABy, {T} ABz, {T} CDx, {T} CDy, {T} CDz, int a0, int b0, int c0, int d0,")
         L.append(f"      double deg, const double* __restrict__ P, double* K, int64_t ld) {{")
@@ -438,7 +447,8 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
                         terms.append(nm if c == 1.0 else f"{fmt(c)} * {nm}")
                 L.append(f"    const {T} s{as_}_{bs}_{jf} = " + " + ".join(terms) + ";")
     # ket HRR + spherical with the missing f as structural zeros, then digestion
-    if mode == "K":
+    ldp = "ldP" if mode == "R" else "ld"
+    if mode in ("K", "R"):
         for bs in range(nbs):
             for ks in ("c", "d"):
                 n = ncs if ks == "c" else nds
@@ -448,14 +458,14 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
         if mode in ("D", "E"):
             L.append("    {")
         else:
-            L.append(f"    {{ const double* Pa = P + (int64_t)(a0 + {as_}) * ld;")
-        if mode == "K":
+            L.append(f"    {{ const double* Pa = P + (int64_t)(a0 + {as_}) * {ldp};")
+        if mode in ("K", "R"):
             L.append("      double kac[%d] = {0}; double kad[%d] = {0};" % (ncs, nds))
         for bs in range(nbs):
             if mode in ("D", "E"):
                 L.append("      {")
             else:
-                L.append(f"      {{ const double* Pb = P + (int64_t)(b0 + {bs}) * ld;")
+                L.append(f"      {{ const double* Pb = P + (int64_t)(b0 + {bs}) * {ldp};")
             names = {}
             for k, n in enumerate(korder):
                 r = krec[n]
@@ -528,6 +538,16 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
         if mode in ("J", "D", "E"):
             L.append("    }")
             continue
+        if mode == "R":
+            L.append(f"      if (wA != 0.0) {{ double* Ka = K + (int64_t)(a0 + {as_}) * ldK;")
+            L.append(f"        for (int x = 0; x < {ncs}; ++x) atomicAdd(&Ka[c0 + x], wA * kac[x]);")
+            L.append(f"        for (int x = 0; x < {nds}; ++x) atomicAdd(&Ka[d0 + x], wA * kad[x]); }}")
+            L.append(f"      if (wC != 0.0) for (int x = 0; x < {ncs}; ++x)")
+            L.append(f"        atomicAdd(&K[(int64_t)(c0 + x) * ldK + a0 + {as_}], wC * kac[x]);")
+            L.append(f"      if (wD != 0.0) for (int x = 0; x < {nds}; ++x)")
+            L.append(f"        atomicAdd(&K[(int64_t)(d0 + x) * ldK + a0 + {as_}], wD * kad[x]);")
+            L.append("    }")
+            continue
         L.append(f"      double* Ka = K + (int64_t)(a0 + {as_}) * ld;")
         L.append(f"      for (int x = 0; x < {ncs}; ++x) atomicAdd(&Ka[c0 + x], deg * kac[x]);")
         L.append(f"      for (int x = 0; x < {nds}; ++x) atomicAdd(&Ka[d0 + x], deg * kad[x]);")
@@ -540,6 +560,24 @@ def emit_digest_part(em, la, lb, lc, ld, name, f_part, mode="K"):
             for ds in range(nds):
                 if (cs, ds) in jtouched:
                     L.append(f"    atomicAdd(&K[(int64_t)(c0 + {cs}) * ld + d0 + {ds}], deg2 * jcd{cs}_{ds});")
+        L.append("  }")
+        return
+    if mode == "R":
+        for bs in range(nbs):
+            L.append(f"    if (wB != 0.0) {{ double* Kb = K + (int64_t)(b0 + {bs}) * ldK;")
+            for cs in range(ncs):
+                L.append(f"      atomicAdd(&Kb[c0 + {cs}], wB * kbc{bs}_{cs});")
+            for ds in range(nds):
+                L.append(f"      atomicAdd(&Kb[d0 + {ds}], wB * kbd{bs}_{ds});")
+            L.append("    }")
+            L.append("    if (wC != 0.0) {")
+            for cs in range(ncs):
+                L.append(f"      atomicAdd(&K[(int64_t)(c0 + {cs}) * ldK + b0 + {bs}], wC * kbc{bs}_{cs});")
+            L.append("    }")
+            L.append("    if (wD != 0.0) {")
+            for ds in range(nds):
+                L.append(f"      atomicAdd(&K[(int64_t)(d0 + {ds}) * ldK + b0 + {bs}], wD * kbd{bs}_{ds});")
+            L.append("    }")
         L.append("  }")
         return
     for bs in range(nbs):
@@ -641,12 +679,12 @@ for _kv in filter(None, os.environ.get("HFX_SPLITS", "").split(",")):
     _k, _v = _kv.split(":")
     DEFAULT_SPLITS[tuple(int(c) for c in _k)] = int(_v)
 
-# FP32 slices: an FP32 value takes half the registers, so fewer slices fit
-# (measured the same way).
-DEFAULT_SPLITS_F32 = {
-    (2, 1, 1, 1): 1, (2, 1, 2, 0): 1, (2, 2, 1, 0): 1, (2, 2, 2, 0): 1,
-    (2, 1, 2, 1): 2, (2, 2, 1, 1): 1, (2, 2, 2, 1): 2, (2, 2, 2, 2): 5,
-}
+# FP32 slices: the same as FP64.  FP32 halves the contracted array but not
+# the rest of a slice's live values (its FP64 large-argument Boys branch, FP64
+# digestion, addresses), and with fewer slices the FP32 kernels spilled
+# 1.6-3.4 KB per lane (compiler resource reports); unpacked FP32 arithmetic
+# runs at the FP64 rate on this chip, so FP32 gains no issue rate either.
+DEFAULT_SPLITS_F32 = dict(DEFAULT_SPLITS)
 for _kv in filter(None, os.environ.get("HFX_SPLITS_F32", "").split(",")):
     _k, _v = _kv.split(":")
     DEFAULT_SPLITS_F32[tuple(int(c) for c in _k)] = int(_v)
@@ -676,6 +714,38 @@ def write_jk_tu(outdir, tag, suffix, nm, kernel, launcher, swap="false"):
         "}  // namespace hfx",
     ]
     write_if_changed(os.path.join(outdir, f"tu_{tag}{suffix}_jk.hip"), "\n".join(tu) + "\n")
+
+
+def write_per_tu(outdir, tag, nm, la, lb, lc, ld):
+    """Periodic builds: the canonical class kernel with the wave's pair as the
+    recurrence's bra (its class the higher one), and -- for classes of two
+    different pair classes -- with the lane's pair as the bra (the wave's
+    pair of the lower class)."""
+    lines = [
+        "// Generated by gen_eri.py; do not edit.",
+        '#include "hfx_device.hpp"',
+        f'#include "eri_{tag}.h"',
+        "namespace hfx {",
+        f"void launch_eriper_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
+        f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,",
+        "                  [&](const QuartetArgs &a, unsigned grid) {",
+        f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri<{nm}, false, false, true>), dim3(grid), dim3(64), 0, s, a);",
+        "                  });",
+        "}",
+    ]
+    if (la, lb) != (lc, ld):
+        lines += [
+            f"void launch_eriperS_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
+            f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,",
+            "                  [&](const QuartetArgs &a, unsigned grid) {",
+            f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri<{nm}, false, true, true>), dim3(grid), dim3(64), 0, s, a);",
+            "                  });",
+            "}",
+        ]
+    else:
+        lines += [f"void launch_eriperS_{tag}(const QuartetArgs &, unsigned, hipStream_t) {{}}"]
+    lines.append("}  // namespace hfx")
+    write_if_changed(os.path.join(outdir, f"tu_{tag}_per.hip"), "\n".join(lines) + "\n")
 
 
 # Classes evaluated with the roles of the pairs exchanged, (cd|ab) in place of
@@ -741,6 +811,7 @@ def emit_struct(em, la, lb, lc, ld, nm, G):
         emit_digest_part(em, la, lb, lc, ld, f"digJ_p{g}", ft, mode="J")
         if em.T == "double":
             emit_digest_part(em, la, lb, lc, ld, f"store_p{g}", ft, mode="E")
+            emit_digest_part(em, la, lb, lc, ld, f"digR_p{g}", ft, mode="R")
         if (la, lb) == (lc, ld):
             emit_digest_part(em, la, lb, lc, ld, f"diag_p{g}", ft, mode="D")
             # largest diagonal value [e0|e0] of the contracted array (bra and
@@ -789,6 +860,16 @@ def emit_struct(em, la, lb, lc, ld, nm, G):
             em.lines.append(f"    {kw} constexpr (W == {g_}) diagE_p{g_}(acc, m);")
         em.lines.append("  }")
     if T_ == "double":
+        # exchange rows chosen per call (periodic builds)
+        em.lines.append("  template <int W> __device__ __forceinline__ static void digR(const %s* __restrict__ acc," % T_)
+        em.lines.append("      double ABx, double ABy, double ABz, double CDx, double CDy, double CDz, int a0, int b0, int c0, int d0,")
+        em.lines.append("      double wA, double wB, double wC, double wD, const double* __restrict__ P, int64_t ldP, double* K,")
+        em.lines.append("      int64_t ldK) {")
+        for g_ in range(G):
+            kw = "if" if g_ == 0 else "else if"
+            em.lines.append(f"    {kw} constexpr (W == {g_}) digR_p{g_}(acc, ABx, ABy, ABz, CDx, CDy, CDz, a0, b0, c0, d0, wA,"
+                            " wB, wC, wD, P, ldP, K, ldK);")
+        em.lines.append("  }")
         # this slice's share of the raw spherical values (hfx_eval_quartets)
         em.lines.append("  template <int W> __device__ __forceinline__ static void store(const %s* __restrict__ acc," % T_)
         em.lines.append("      double ABx, double ABy, double ABz, double CDx, double CDy, double CDz, int64_t sab,")
@@ -898,6 +979,7 @@ def generate(outdir, T="double", splits=None):
         tu.append("}  // namespace hfx")
         write_if_changed(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "\n".join(tu) + "\n")
         write_jk_tu(outdir, tag, suffix, dn, "k_eri", "launch_erijk", sw)
+        write_per_tu(outdir, tag, nm, la, lb, lc, ld)
     return model
 
 

@@ -12,8 +12,9 @@
 //            primitive pair's own Schwarz factor B, so that every primitive
 //            quartet contributes at most B_ab B_cd to any integral.  The
 //            records of a pair are sorted by B, largest first.
-//   Boys     table T_L[i][k] = F_(L+k)(i h) / k!, h = 1/16, i <= 576, k < 8,
-//            one 8-double row per grid point and L.
+//   Boys     table T_L[i][k] = F_(L+k)(i h) / k! for k < 7 and T_L[i][7] =
+//            exp(-i h), h = 1/32, i <= 1152: one 64-byte row per grid point
+//            and L.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -63,30 +64,31 @@ __device__ __forceinline__ PrimRec32 load_rec(CPrimRec32 *r) {
     return x;
 }
 
-constexpr int BOYS_NROW = 577;          // grid points 0 .. 36 step 1/16
-constexpr double BOYS_H = 1.0 / 16.0;
-constexpr double BOYS_INVH = 16.0;
+constexpr int BOYS_NROW = 1153;         // grid points 0 .. 36 step 1/32
+constexpr double BOYS_H = 1.0 / 32.0;
+constexpr double BOYS_INVH = 32.0;
 constexpr double BOYS_TMAX = 36.0;
-constexpr int BOYS_NTAY = 8;            // Taylor terms
+constexpr int BOYS_NTAY = 8;            // doubles per row: 7 Taylor terms and exp(-x_i)
 constexpr int BOYS_LMAX = 8;            // highest L = 4 * lmax
 constexpr int BOYS_TAB_SIZE = (BOYS_LMAX + 1) * BOYS_NROW * BOYS_NTAY;
 
 // F_m(x), m = 0..L.  x < 36: Taylor expansion of F_L around the nearest grid
-// point from the table, then the downward recursion
-// F_m = (2x F_(m+1) + e^-x) / (2m+1).  x >= 36: F_0 = sqrt(pi/(4x)) (erf(sqrt x)
-// equals 1 to 2e-17 there), then the upward recursion
-// F_(m+1) = ((2m+1) F_m - e^-x) / (2x), stable for x > L.
+// point x_i (|u| = |x_i - x| <= 1/64, seven terms: truncation below 5e-17
+// relative), e^-x = e^-x_i e^u with e^u to sixth order (same bound), then the
+// downward recursion F_m = (2x F_(m+1) + e^-x) / (2m+1).  x >= 36: F_0 =
+// sqrt(pi/(4x)) (erf(sqrt x) equals 1 to 2e-17 there), then the upward
+// recursion F_(m+1) = ((2m+1) F_m - e^-x) / (2x), stable for x > L; there e^-x
+// weighs at most 6e-9 of (2m+1) F_m (m <= 8), so the FP32 exponential (relative
+// error ~2e-7) changes F_m by ~1e-15 relative at most.
 template <int L>
 __device__ __forceinline__ void boys(double x, const double *__restrict__ tab, double *F) {
-    const double ex = exp(-x);
     if (x < BOYS_TMAX) {
         const int i = __double2int_rn(x * BOYS_INVH);
         const double u = i * BOYS_H - x;
         const double *r = tab + ((size_t)L * BOYS_NROW + i) * BOYS_NTAY;
         const double4 lo = *reinterpret_cast<const double4 *>(r);
         const double4 hi = *reinterpret_cast<const double4 *>(r + 4);
-        double f = hi.w;
-        f = fma(f, u, hi.z);
+        double f = hi.z;
         f = fma(f, u, hi.y);
         f = fma(f, u, hi.x);
         f = fma(f, u, lo.w);
@@ -94,10 +96,18 @@ __device__ __forceinline__ void boys(double x, const double *__restrict__ tab, d
         f = fma(f, u, lo.y);
         f = fma(f, u, lo.x);
         F[L] = f;
+        double e = fma(u, 1.0 / 720.0, 1.0 / 120.0);
+        e = fma(e, u, 1.0 / 24.0);
+        e = fma(e, u, 1.0 / 6.0);
+        e = fma(e, u, 0.5);
+        e = fma(e, u, 1.0);
+        e = fma(e, u, 1.0);
+        const double ex = hi.w * e;
         const double x2 = 2.0 * x;
 #pragma unroll
         for (int m = L - 1; m >= 0; --m) F[m] = fma(x2, F[m + 1], ex) * (1.0 / (2 * m + 1));
     } else {
+        const double ex = (double)__expf(-(float)x);
         const double rs = rsqrt(x);
         F[0] = 0.88622692545275801365 * rs;  // sqrt(pi)/2
         const double h = 0.5 * rs * rs;       // 1/(2x)
@@ -107,7 +117,7 @@ __device__ __forceinline__ void boys(double x, const double *__restrict__ tab, d
 }
 
 // FP32 Boys: x < 36 from the FP32 table (Taylor to fourth order around the
-// nearest grid point, |u| <= 1/32, truncation below 3e-10 relative) and the
+// nearest grid point, |u| <= 1/64, truncation below 1e-11 relative) and the
 // downward recursion in FP32; x >= 36 in FP64 (F_0 then upward), rounded.
 template <int L>
 __device__ __forceinline__ void boys32(float x, const float *__restrict__ tab, float *F) {
@@ -278,6 +288,12 @@ struct QuartetArgs {
     int32_t dens;
     int32_t nsh;              // shells (pmax is nsh x nsh)
     const double *pmax;       // largest |P| of every shell block
+    // Periodic builds: the bra pairs contain a home-cell shell (index <
+    // nhome), every (bra, ket) combination is evaluated (no unique-quartet
+    // rule), and only K rows of home-cell shells are digested, into K with
+    // its own leading dimension ldK.
+    int32_t nhome;
+    int64_t ldK;
     int32_t op;
     double om2;               // omega^2
     double prim_tau;          // primitive quartets with B_ab B_cd < prim_tau may be skipped
@@ -409,7 +425,7 @@ __device__ __forceinline__ void ket_tiles(const QuartetArgs &a, int p, const Pai
 // SWAP: C is the class with the pairs' roles exchanged, (cd|ab): the lane's
 // ket record enters the recurrence as its bra and the wave's bra record as
 // its ket, and the digestion images are the transposes of the usual ones.
-template <class C, int W, int VRRW, bool WJ, bool SWAP>
+template <class C, int W, int VRRW, bool WJ, bool SWAP, bool PER>
 __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, int lo, int cut) {
     const PairHdr bh = a.hdr[a.bra_ids[p]];
     const int nkp = a.ket_gnp[g];
@@ -450,7 +466,19 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
                                          a.boys, acc, a.om);
             }
         }
-        if (act) {
+        if constexpr (PER) {
+            if (act) {
+                // rows of the wave's pair that lie in the home cell; both orders of
+                // the lane's pair are digested (half each when its shells coincide)
+                const double dk = kh.diag ? 0.5 : 1.0;
+                const double hA = bh.shA < a.nhome ? dk : 0.0;
+                const double hB = (bh.shB < a.nhome && !bh.diag) ? dk : 0.0;
+                const PairHdr &x = SWAP ? kh : bh, &y = SWAP ? bh : kh;
+                C::template digR<W>(acc, x.ABx, x.ABy, x.ABz, y.ABx, y.ABy, y.ABz, x.bfA, x.bfB, y.bfA, y.bfB,
+                                    SWAP ? 0.0 : hA, SWAP ? 0.0 : hB, SWAP ? hA : 0.0, SWAP ? hB : 0.0, a.P, a.ld,
+                                    a.K, a.ldK);
+            }
+        } else if (act) {
             double deg = 1.0;
             if (bh.diag) deg *= 0.5;
             if (kh.diag) deg *= 0.5;
@@ -469,12 +497,12 @@ __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, in
     }
 }
 
-template <class C, int W, bool WJ = false, bool SWAP = false>
+template <class C, int W, bool WJ = false, bool SWAP = false, bool PER = false>
 __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p, int g, int lo, int cut) {
     if (w == W) {
-        tile_part<C, W, W, WJ, SWAP>(a, p, g, lo, cut);
+        tile_part<C, W, W, WJ, SWAP, PER>(a, p, g, lo, cut);
     } else if constexpr (W + 1 < C::NSPLIT) {
-        tile_dispatch<C, W + 1, WJ, SWAP>(a, w, p, g, lo, cut);
+        tile_dispatch<C, W + 1, WJ, SWAP, PER>(a, w, p, g, lo, cut);
     }
 }
 
@@ -485,7 +513,8 @@ __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p
 // recomputed per slice instead of exchanged.
 // WJ: also digest the Coulomb matrix J from the same quartet values.
 // SWAP: C is the exchanged class (see tile_part).
-template <class C, bool WJ = false, bool SWAP = false>
+// PER: periodic build (see QuartetArgs::nhome).
+template <class C, bool WJ = false, bool SWAP = false, bool PER = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri(QuartetArgs a) {
     const int lb0 = xcd_block(a.nblk, 8 * C::NSPLIT);
     if (lb0 < 0) return;
@@ -503,7 +532,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     const int lo2 = lo + sub * a.tq;
     const int cut2 = min(cut, lo2 + a.tq);
     if (cut2 <= lo2) return;
-    tile_dispatch<C, 0, WJ, SWAP>(a, w, p, g, lo2, cut2);
+    tile_dispatch<C, 0, WJ, SWAP, PER>(a, w, p, g, lo2, cut2);
 }
 
 // FP32 counterpart of tile_part: FP32 records, recurrences and contraction,

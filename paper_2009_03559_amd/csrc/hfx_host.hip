@@ -43,16 +43,16 @@ hfx_status fail(hfx_status s, const std::string &msg) {
     } while (0)
 
 // ---------------------------------------------------------------- Boys ----
-// F_m(x) on the grid x_i = i/16, m = 0..15, in long double: the top order by
+// F_m(x) on the grid x_i = i/32, m = 0..14, in long double: the top order by
 // its power series  F_M(x) = e^-x sum_k (2x)^k / ((2M+1)(2M+3)...(2M+2k+1)),
 // the lower orders by the stable downward recursion.  Stored as
-// T_L[i][k] = F_(L+k)(x_i) / k!.
+// T_L[i][k] = F_(L+k)(x_i) / k! for k = 0..6 and T_L[i][7] = e^-x_i.
 static std::vector<double> make_boys_table() {
-    const int M = BOYS_LMAX + BOYS_NTAY - 1;
+    const int M = BOYS_LMAX + BOYS_NTAY - 2;
     std::vector<double> tab((size_t)BOYS_TAB_SIZE);
     std::vector<long double> F(M + 1);
     for (int i = 0; i < BOYS_NROW; ++i) {
-        long double x = (long double)i / 16.0L;
+        long double x = (long double)i / 32.0L;
         long double term = 1.0L / (2 * M + 1), sum = term;
         for (int k = 1; k < 4000; ++k) {
             term *= 2.0L * x / (2 * M + 2 * k + 1);
@@ -64,10 +64,11 @@ static std::vector<double> make_boys_table() {
         for (int m = M - 1; m >= 0; --m) F[m] = (2.0L * x * F[m + 1] + ex) / (2 * m + 1);
         for (int L = 0; L <= BOYS_LMAX; ++L) {
             long double fact = 1.0L;
-            for (int k = 0; k < BOYS_NTAY; ++k) {
+            for (int k = 0; k < BOYS_NTAY - 1; ++k) {
                 if (k > 0) fact *= k;
                 tab[((size_t)L * BOYS_NROW + i) * BOYS_NTAY + k] = (double)(F[L + k] / fact);
             }
+            tab[((size_t)L * BOYS_NROW + i) * BOYS_NTAY + BOYS_NTAY - 1] = (double)ex;
         }
     }
     return tab;
@@ -166,6 +167,12 @@ __global__ void k_fill(double *K, int64_t n, int64_t ld) {
     K[(t / n) * ld + t % n] = 0.0;
 }
 
+__global__ void k_fill_rect(double *K, int64_t rows, int64_t cols, int64_t ld) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * cols) return;
+    K[(t / cols) * ld + t % cols] = 0.0;
+}
+
 __global__ void k_fill_u64(unsigned long long *c, int n) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) c[t] = 0ull;
@@ -245,6 +252,11 @@ __global__ void k_asym(const double *P, int64_t n, int64_t ld, double *part) {
                          const double *, double *, hipStream_t);
 HFX_FOR_CLASSES(DECL)
 #undef DECL
+#define DECLPER(T)                                                          \
+    void launch_eriper_##T(const QuartetArgs &, unsigned, hipStream_t);    \
+    void launch_eriperS_##T(const QuartetArgs &, unsigned, hipStream_t);
+HFX_FOR_CLASSES(DECLPER)
+#undef DECLPER
 #define DECL32(T)                                                           \
     void launch_eri32_##T(const QuartetArgs &, unsigned, hipStream_t);     \
     void launch_erijk_##T(const QuartetArgs &, unsigned, hipStream_t);     \
@@ -289,6 +301,18 @@ static const eri_fn k_erijk_tab[21] = {
 };
 static const eri_fn k_erijk32_tab[21] = {
 #define E(T) launch_erijk32_##T,
+    HFX_FOR_CLASSES(E)
+#undef E
+};
+// periodic builds: canonical class, wave's pair as the recurrence's bra
+// (class of the wave's pair >= the lane's) or lane's pair as the bra
+static const eri_fn k_eriper_tab[21] = {
+#define E(T) launch_eriper_##T,
+    HFX_FOR_CLASSES(E)
+#undef E
+};
+static const eri_fn k_eriperS_tab[21] = {
+#define E(T) launch_eriperS_##T,
     HFX_FOR_CLASSES(E)
 #undef E
 };
@@ -561,7 +585,7 @@ hfx_pairs_s::~hfx_pairs_s() {
 }
 
 void hfx_pairs_s::drop_lists() {
-    for (ClassList *set : {lists, mlists})
+    for (ClassList *set : {lists, mlists, hlists})
         for (int i = 0; i < 6; ++i) {
             ClassList &c = set[i];
             hipFree(c.d_ids);
@@ -575,6 +599,7 @@ void hfx_pairs_s::drop_lists() {
         }
     lists_valid = false;
     mlists_valid = false;
+    hlists_valid = false;
 }
 
 extern "C" void hfx_pairs_destroy(hfx_pairs p) { delete p; }
@@ -1081,6 +1106,178 @@ extern "C" hfx_status hfx_eval_quartets(hfx_pairs p, const hfx_opts *o, int64_t 
                                 dst[((cc * nL + d) * nI + a) * nJ + b] = v;
                         }
         }
+    }
+    return HFX_OK;
+}
+
+// ------------------------------------------------------------- periodic ----
+namespace hfx {
+
+// Kept pairs with at least one shell in the home cell (shell index < nhome),
+// per pair class, in the layout of the other lists (groups of equal
+// primitive-pair count, Q descending): the bra side of periodic builds.
+static hfx_status build_home_lists(hfx_pairs p, double tau, int nhome, hipStream_t st) {
+    if (p->hlists_valid && p->hlist_tau == tau && p->hlist_nhome == nhome) return HFX_OK;
+    for (int c = 0; c < 6; ++c) {
+        ClassList &L = p->hlists[c];
+        hipFree(L.d_ids);
+        hipFree(L.d_Q);
+        hipFree(L.d_grp);
+        hipFree(L.d_goff);
+        hipFree(L.d_gnp);
+        L = ClassList();
+    }
+    double qmax = 0.0;
+    for (double q : p->Q) qmax = std::max(qmax, q);
+    for (int c = 0; c < 6; ++c) {
+        std::vector<int32_t> ids;
+        for (int32_t id : p->class_ids[c]) {
+            const PairHdr &h = p->hdr_host[id];
+            if ((h.shA < nhome || h.shB < nhome) && p->Q[id] * qmax >= tau) ids.push_back(id);
+        }
+        std::sort(ids.begin(), ids.end(), [&](int32_t x, int32_t y) {
+            const int nx = p->hdr_host[x].n, ny = p->hdr_host[y].n;
+            if (nx != ny) return nx < ny;
+            if (p->Q[x] != p->Q[y]) return p->Q[x] > p->Q[y];
+            return x < y;
+        });
+        ClassList &L = p->hlists[c];
+        L.n = (int)ids.size();
+        if (!L.n) continue;
+        std::vector<double> q(L.n);
+        std::vector<int32_t> grp(L.n);
+        for (int i = 0; i < L.n; ++i) {
+            q[i] = p->Q[ids[i]];
+            const int np = p->hdr_host[ids[i]].n;
+            if (L.gnp.empty() || L.gnp.back() != np) {
+                L.gnp.push_back(np);
+                L.goff.push_back(i);
+            }
+            grp[i] = (int)L.gnp.size() - 1;
+        }
+        L.goff.push_back(L.n);
+        L.ngrp = (int)L.gnp.size();
+        HIPCHK(hipMalloc(&L.d_ids, L.n * sizeof(int32_t)));
+        HIPCHK(hipMalloc(&L.d_Q, L.n * sizeof(double)));
+        HIPCHK(hipMalloc(&L.d_grp, L.n * sizeof(int32_t)));
+        HIPCHK(hipMalloc(&L.d_goff, L.goff.size() * sizeof(int32_t)));
+        HIPCHK(hipMalloc(&L.d_gnp, L.gnp.size() * sizeof(int32_t)));
+        HIPCHK(hipMemcpyAsync(L.d_ids, ids.data(), L.n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.d_Q, q.data(), L.n * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.d_grp, grp.data(), L.n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.d_goff, L.goff.data(), L.goff.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.d_gnp, L.gnp.data(), L.gnp.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));  // the host vectors die here
+        L.h_ids = std::move(ids);
+        L.h_Q = std::move(q);
+        L.h_grp = std::move(grp);
+    }
+    p->hlists_valid = true;
+    p->hlist_tau = tau;
+    p->hlist_nhome = nhome;
+    return HFX_OK;
+}
+
+}  // namespace hfx
+
+extern "C" hfx_status hfx_build_K_periodic(hfx_pairs p, int32_t nhome_shell, const double *P_dev, int64_t ldP,
+                                           double *K_dev, int64_t ldK, const hfx_opts *o, void *stream,
+                                           hfx_stats *st_out) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p) return fail(HFX_EINVAL, "pairs is NULL");
+    if (!P_dev || !K_dev) return fail(HFX_EINVAL, "P or K is NULL");
+    hfx_status s = check_opts(o);
+    if (s != HFX_OK) return s;
+    if (o->prec != HFX_PREC_FP64) return fail(HFX_EUNSUPPORTED, "periodic builds are FP64 only");
+    if (o->flags) return fail(HFX_EUNSUPPORTED, "periodic builds take no flags");
+    if (nhome_shell < 1 || nhome_shell > p->nshell) return fail(HFX_EINVAL, "nhome_shell not in [1, nshell]");
+    const int64_t n = p->nbf, nh = p->bfo[nhome_shell];
+    if (ldP < n || ldK < n) return fail(HFX_EINVAL, "ldP or ldK < n_bf");
+    if (K_dev < P_dev + (n - 1) * ldP + n && P_dev < K_dev + (nh - 1) * ldK + n)
+        return fail(HFX_EINVAL, "K aliases P");
+    hipStream_t st = (hipStream_t)stream;
+    s = check_P(P_dev, n, ldP, st, p->d_part);
+    if (s != HFX_OK) return s;
+    s = compute_bounds(p, o, st);
+    if (s != HFX_OK) return s;
+    s = build_lists(p, o->tau, false, st);
+    if (s != HFX_OK) return s;
+    s = build_home_lists(p, o->tau, nhome_shell, st);
+    if (s != HFX_OK) return s;
+    unsigned long long *cnt = st_out ? p->d_count : nullptr;
+    if (cnt) hipLaunchKernelGGL(k_fill_u64, dim3(2), dim3(64), 0, st, cnt, NCOUNT);
+    hipLaunchKernelGGL(k_fill_rect, dim3((unsigned)((nh * n + 255) / 256)), dim3(256), 0, st, K_dev, nh, n, ldK);
+    HIPCHK(hipGetLastError());
+    if (st_out) HIPCHK(hipEventRecord(p->ev[0], st));
+    const int op = kernel_op(o);
+    for (int cb = 0; cb < 6; ++cb)
+        for (int ck = 0; ck < 6; ++ck) {
+            const ClassList &B = p->hlists[cb], &Kl = p->lists[ck];
+            if (!B.n || !Kl.n) continue;
+            const int hi = std::max(cb, ck), lo = std::min(cb, ck), ci = hi * (hi + 1) / 2 + lo;
+            QuartetArgs a{};
+            a.hdr = p->d_hdr;
+            a.prim = p->d_prim;
+            a.bra_ids = B.d_ids;
+            a.bra_Q = B.d_Q;
+            a.bra_grp = B.d_grp;
+            a.n_bra = B.n;
+            a.bra_first = 0;
+            a.bra_stride = 1;
+            a.ket_ids = Kl.d_ids;
+            a.ket_Q = Kl.d_Q;
+            a.ket_goff = Kl.d_goff;
+            a.ket_gnp = Kl.d_gnp;
+            a.n_kgrp = Kl.ngrp;
+            a.same = 0;
+            a.op = op;
+            a.om2 = op ? o->omega * o->omega : 0.0;
+            a.om = op ? o->omega : 0.0;
+            a.prim_tau = o->prim_tau;
+            a.boys = p->d_boys;
+            a.P = P_dev;
+            a.K = K_dev;
+            a.ld = ldP;
+            a.ldK = ldK;
+            a.nhome = nhome_shell;
+            a.tau = o->tau;
+            a.tau_hi = HUGE_VAL;
+            a.count = cnt ? cnt + 4 * ci : nullptr;
+            int gmax = 1;
+            for (size_t gi = 0; gi + 1 < Kl.goff.size(); ++gi) gmax = std::max(gmax, Kl.goff[gi + 1] - Kl.goff[gi]);
+            const int L = PAIR_L[cb][0] + PAIR_L[cb][1] + PAIR_L[ck][0] + PAIR_L[ck][1];
+            a.tq = quartet_block(L);
+            a.nsub = (gmax + a.tq - 1) / a.tq;
+            const int64_t nblk = (int64_t)B.n * Kl.ngrp * a.nsub;
+            if (nblk > (int64_t)UINT32_MAX) return fail(HFX_EUNSUPPORTED, "grid too large");
+            // the class kernel of (hi|lo): the wave's pair is its bra when
+            // its class is the higher one, else the lane's pair is
+            (cb >= ck ? k_eriper_tab : k_eriperS_tab)[ci](a, (unsigned)nblk, st);
+            HIPCHK(hipGetLastError());
+        }
+    if (st_out) HIPCHK(hipEventRecord(p->ev[1], st));
+    if (st_out) {
+        unsigned long long h[NCOUNT];
+        HIPCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::memset(st_out, 0, sizeof(*st_out));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+        st_out->device_s = ms * 1e-3;
+        const double *mv = model_vrr(), *mp = model_post();
+        for (int c = 0; c < HFX_NCLASS; ++c) {
+            int cb = 0;
+            while ((cb + 1) * (cb + 2) / 2 <= c) ++cb;
+            const int ck = c - cb * (cb + 1) / 2;
+            const int L = PAIR_L[cb][0] + PAIR_L[cb][1] + PAIR_L[ck][0] + PAIR_L[ck][1];
+            const double nq = (double)h[4 * c], npq = (double)h[4 * c + 1];
+            st_out->class_quartets[c] = (int64_t)h[4 * c];
+            st_out->class_flops[c] = (mv[c] + model_prim_overhead(kernel_op(o), L)) * npq + mp[c] * nq;
+            st_out->quartets += st_out->class_quartets[c];
+            st_out->prim_quartets += (int64_t)npq;
+            st_out->flops += st_out->class_flops[c];
+        }
+        st_out->latency_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return HFX_OK;
 }

@@ -97,6 +97,10 @@ struct hfx_pairs_s {
     bool mlists_valid = false;  // mixed-precision lists: groups of equal count and error-scale bin
     double mlist_tau = -1.0;
     hfx::ClassList mlists[6];
+    bool hlists_valid = false;  // periodic builds: kept pairs with a home-cell shell
+    double hlist_tau = -1.0;
+    int hlist_nhome = -1;
+    hfx::ClassList hlists[6];
     void drop_lists();
     ~hfx_pairs_s();
 };
