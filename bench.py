@@ -55,18 +55,24 @@ def parse():
     ap.add_argument("--no-density", action="store_true", help="skip the density-screened leg")
     ap.add_argument("--no-periodic", action="store_true", help="skip the periodic leg")
     ap.add_argument("--batch-natom", type=str, default="6,20",
-                    help="atom-count range of the batched systems (scaled-down config-3 recipe)")
+                    help="atom-count range of the batched systems (scaled-down uneven-batch recipe)")
     ap.add_argument("--serve-natom", type=str, default="6,24",
-                    help="atom-count range of served requests (scaled-down config-4 recipe)")
+                    help="atom-count range of served requests (scaled-down serving recipe)")
     ap.add_argument("--serve-requests", type=int, default=12)
     ap.add_argument("--no-latency", action="store_true", help="skip the full K-build latency leg")
     ap.add_argument("--latency-natom", type=int, default=64,
                     help="atoms of the lattice (256-atom workload recipe) built whole in the latency leg")
     ap.add_argument("--latency-builds", type=int, default=10)
-    ap.add_argument("--config2", action="store_true",
+    ap.add_argument("--dzp1024", action="store_true",
                     help="only the 1024-atom mixed-precision workload: full K of the 128-atom subset in FP64 and "
                          "mixed, and one shard of the 1024-atom build")
-    ap.add_argument("--config2-shards", type=int, default=2048)
+    ap.add_argument("--dzp1024-shards", type=int, default=2048)
+    ap.add_argument("--serve-mix", type=int, default=0, metavar="N",
+                    help="only run a served mix of 16 small requests x 3 builds with N builds in flight "
+                         "(for kernel traces)")
+    ap.add_argument("--kernel-overlap", type=str, default=None, metavar="DIR",
+                    help="only summarise a rocprofv3 kernel trace under DIR: time with quartet kernels of two "
+                         "or more queues running at once")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 512 MiB device copy five times (HBM counter calibration)")
     return ap.parse_args()
@@ -115,13 +121,13 @@ def cpu_baseline(sysm, tau, omega, budget_s):
 
 
 def batch_leg(a, hfx, hi, torch):
-    """64 independent systems (config-3 recipe: uniform atom counts, l_max in
-    {1, 2}, config-1 shells and P) in one persistent launch per class through
+    """64 independent systems (uneven-batch recipe: uniform atom counts, l_max in
+    {1, 2}, lattice shells and P) in one persistent launch per class through
     the device work queue, FP64 and mixed, against building them one by one."""
     lo, hi_ = (int(x) for x in a.batch_natom.split(","))
-    systems = hi.config3(seed=3, nsys=64, natom_range=(lo, hi_))
+    systems = hi.uneven_batch(seed=3, nsys=64, natom_range=(lo, hi_))
     tau, omega = 1e-10, hi.OMEGA_HSE
-    res = {"workload": f"64 systems, atoms uniform in [{lo},{hi_}] (config-3 recipe scaled down from [20,400]), "
+    res = {"workload": f"64 systems, atoms uniform in [{lo},{hi_}] (uneven-batch recipe scaled down from [20,400]), "
                        f"l_max in {{1,2}}, erfc omega={omega}, tau={tau}"}
     for name, prec in (("fp64", hfx.PREC_FP64), ("mixed", hfx.PREC_MIXED)):
         o = hfx.opts(tau=tau, omega=omega, prec=prec, mixed_cut=a.mixed_cut)
@@ -152,7 +158,7 @@ def batch_leg(a, hfx, hi, torch):
 
 
 def serve_leg(a, hfx, hi, torch):
-    """Served K-builds (config-4 recipe scaled down): requests with log-uniform
+    """Served K-builds (serving recipe scaled down): requests with log-uniform
     atom counts, each 10 SCF-like iterations with P perturbed by 1e-3 relative
     noise, Poisson arrivals at 70 % of the measured closed-loop capacity,
     mixed precision, pair data resident, admission by an HBM budget."""
@@ -215,7 +221,7 @@ def serve_leg(a, hfx, hi, torch):
     wall2, bl2, rl2, nq2 = run(list(arr))
     pct = lambda v, q: float(np.percentile(v, q))
     return {
-        "workload": f"{len(reqs)} requests, atoms log-uniform in [{lo},{hi_}] (config-4 recipe scaled down from "
+        "workload": f"{len(reqs)} requests, atoms log-uniform in [{lo},{hi_}] (serving recipe scaled down from "
                     f"[50,2000]), 10 iterations each, P x (1 + 1e-3 E_t), mixed cut {a.mixed_cut}, "
                     f"HBM budget {budget >> 30} GiB, 4 in flight",
         "capacity_req_per_s": cap,
@@ -317,6 +323,69 @@ def traffic_for(kernel_tag, shards):
     return t.get("hbm_bytes_per_launch")
 
 
+def serve_mix(n_inflight):
+    """Served mix for kernel traces: 16 requests of 4-10 atoms (the
+    lattice workload's shells), 3 SCF-like builds each, all released at once; bounds and lists
+    resident before the mix starts."""
+    import torch
+
+    import hfx_inputs as hi
+    import paper_2009_03559_amd as hfx
+
+    torch.cuda.init()
+    rng = np.random.default_rng(5)
+    systems = [hi.lattice_system(int(n), seed=100 + i) for i, n in enumerate(rng.integers(4, 11, size=16))]
+    o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
+    pairs = [hfx.pairs_from_system(s, o) for s in systems]
+    Ps = [torch.from_numpy(s.P).cuda() for s in systems]
+    Ks = [torch.empty_like(P) for P in Ps]
+    for p, P, K in zip(pairs, Ps, Ks):
+        hfx.build_K(p, P, K, o)
+    torch.cuda.synchronize()
+    srv = hfx.Server(1 << 34, max_inflight=n_inflight)
+    t0 = time.perf_counter()
+    left = {i: 3 for i in range(len(systems))}
+    ticket = {i: srv.submit(pairs[i], Ps[i], Ks[i], o) for i in left}
+    while ticket:
+        for i in list(ticket):
+            done, _ = srv.poll(ticket[i])
+            if done:
+                left[i] -= 1
+                if left[i]:
+                    ticket[i] = srv.submit(pairs[i], Ps[i], Ks[i], o)
+                else:
+                    del ticket[i]
+        time.sleep(0.0005)
+    print(json.dumps({"served_mix": f"{len(systems)} requests x 3 builds", "in_flight": n_inflight,
+                      "wall_s": time.perf_counter() - t0}), flush=True)
+
+
+def kernel_overlap(d):
+    """Quartet-kernel dispatches of a rocprofv3 kernel trace (CSV under d):
+    busy time (any running) and time with kernels of two or more queues
+    running at once."""
+    import csv
+    import glob
+
+    f = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)[0]
+    ev = []
+    with open(f) as fh:
+        for r in csv.DictReader(fh):
+            if "k_eri" in r.get("Kernel_Name", ""):
+                ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r.get("Queue_Id", "0")))
+    pts = sorted([(s_, 1, q) for s_, e_, q in ev] + [(e_, -1, q) for s_, e_, q in ev])
+    active, busy, over, t_prev = {}, 0, 0, None
+    for t, dlt, q in pts:
+        if t_prev is not None:
+            nq = sum(1 for v in active.values() if v > 0)
+            busy += (t - t_prev) if nq >= 1 else 0
+            over += (t - t_prev) if nq >= 2 else 0
+        active[q] = active.get(q, 0) + dlt
+        t_prev = t
+    print(json.dumps({"dispatches": len(ev), "queues": len({q for _, _, q in ev}), "busy_ms": busy / 1e6,
+                      "overlap_ms": over / 1e6, "overlap_fraction": over / max(busy, 1)}), flush=True)
+
+
 def copy_calibration():
     import torch
     n = (512 << 20) // 8
@@ -350,8 +419,8 @@ def screened_count(s, Q, tau):
     return total
 
 
-def config2_leg(a):
-    """Mixed precision on the config-1 recipe at 1024 atoms (13312 functions).
+def dzp1024_leg(a):
+    """Mixed precision on the 256-atom lattice recipe at 1024 atoms (13312 functions).
     The 128 atoms nearest the centroid: full K in FP64 (the parity-checked
     path) and in mixed precision, max-abs and tr(PK) differences, speedup.
     The 1024-atom system: one bra-pair shard in FP64 and mixed."""
@@ -362,9 +431,9 @@ def config2_leg(a):
 
     torch.cuda.init()
     tau, omega = 1e-10, hi.OMEGA_HSE
-    big = hi.config2()
-    sub = hi.config2_subset(big, 128)
-    out = {"metric": "config-2 mixed precision", "workload": f"config-1 recipe at 1024 atoms ({big.nbf} functions); "
+    big = hi.dzp1024_lattice()
+    sub = hi.central_subset(big, 128)
+    out = {"metric": "1024-atom lattice, mixed precision", "workload": f"256-atom lattice recipe at 1024 atoms ({big.nbf} functions); "
            f"128-atom subset nearest the centroid ({sub.nbf} functions)", "mixed_cut": a.mixed_cut}
     res = {}
     pairs = hfx.pairs_from_system(sub)
@@ -399,14 +468,14 @@ def config2_leg(a):
         o = hfx.opts(tau=tau, omega=omega, prec=prec, mixed_cut=a.mixed_cut)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = hfx.build_K_shard(pb, Pb, Kb, o, 0, a.config2_shards, stats=True)
+        st = hfx.build_K_shard(pb, Pb, Kb, o, 0, a.dzp1024_shards, stats=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         shard[name] = {"s": dt, "quartets": st["quartets"], "quartets_per_s": st["quartets"] / dt,
-                       "projected_full_build_s": st["device_s"] * a.config2_shards}
+                       "projected_full_build_s": st["device_s"] * a.dzp1024_shards}
         print(f"# 1024-atom shard {name}: {dt:.2f} s", file=sys.stderr, flush=True)
     shard["speedup"] = shard["fp64"]["s"] / shard["mixed"]["s"]
-    out["shard_of_1024"] = dict(shard, shards=a.config2_shards)
+    out["shard_of_1024"] = dict(shard, shards=a.dzp1024_shards)
     print(json.dumps(out), flush=True)
 
 
@@ -415,8 +484,14 @@ def main():
     if a.copy_calib:
         copy_calibration()
         return
-    if a.config2:
-        config2_leg(a)
+    if a.serve_mix:
+        serve_mix(a.serve_mix)
+        return
+    if a.kernel_overlap:
+        kernel_overlap(a.kernel_overlap)
+        return
+    if a.dzp1024:
+        dzp1024_leg(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported in this build "
@@ -431,7 +506,7 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     tau, omega = 1e-10, hi.OMEGA_HSE
-    sysm = hi.config1() if a.natom == 256 else hi.lattice_system(a.natom, seed=1, name=f"lattice_dzp{a.natom}")
+    sysm = hi.dzp256_lattice() if a.natom == 256 else hi.lattice_system(a.natom, seed=1, name=f"lattice_dzp{a.natom}")
     o = hfx.opts(tau=tau, omega=omega)
     torch.cuda.synchronize()
     t_setup = time.perf_counter()

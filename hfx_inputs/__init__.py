@@ -27,11 +27,11 @@ __all__ = [
     "System",
     "tiny_sp_cluster",
     "lattice_system",
-    "config0",
-    "config1",
-    "config2",
-    "config2_subset",
-    "config3",
+    "sp8_cluster",
+    "dzp256_lattice",
+    "dzp1024_lattice",
+    "central_subset",
+    "uneven_batch",
     "served_requests",
     "si64_like",
     "periodic_cluster",
@@ -150,12 +150,12 @@ def tiny_sp_cluster(seed: int = 0, natom: int = 8, box: float = 10.0, min_sep: f
     return _pack(xyz, shells, P, dict(name="tiny_sp_cluster", seed=seed, natom=natom))
 
 
-def config0(seed: int = 0) -> System:
+def sp8_cluster(seed: int = 0) -> System:
     """8 atoms in a 10-bohr cube (min separation 1.8), one s and one p shell of
     3 primitives each (alpha log-uniform in [0.1, 10], c uniform in [0.1, 1]),
     32 functions; P = 2 C C^T from 8 random orthonormal columns."""
     s = tiny_sp_cluster(seed=seed)
-    s.meta["name"] = "config0_tiny_sp8"
+    s.meta["name"] = "sp8_cluster"
     return s
 
 
@@ -206,17 +206,17 @@ def lattice_system(natom: int, seed: int, lmax: int = 2, name: str = "lattice_dz
     return _pack(xyz, shells, P, dict(name=name, seed=seed, natom=natom, lmax=lmax))
 
 
-def config1(seed: int = 1) -> System:
+def dzp256_lattice(seed: int = 1) -> System:
     """256-atom DZP-like lattice system, 1280 shells, 3328 functions."""
-    return lattice_system(256, seed, name="config1_dzp256")
+    return lattice_system(256, seed, name="dzp256_lattice")
 
 
-def config2(seed: int = 2) -> System:
-    """The config-1 recipe at 1024 atoms, 13312 functions."""
-    return lattice_system(1024, seed, name="config2_dzp1024")
+def dzp1024_lattice(seed: int = 2) -> System:
+    """The 256-atom lattice recipe at 1024 atoms, 13312 functions."""
+    return lattice_system(1024, seed, name="dzp1024_lattice")
 
 
-def config2_subset(sys: System, natom: int = 128) -> System:
+def central_subset(sys: System, natom: int = 128) -> System:
     """The `natom` atoms nearest the centroid (ties by index)."""
     c = sys.xyz.mean(axis=0)
     d = np.linalg.norm(sys.xyz - c, axis=1)
@@ -224,9 +224,9 @@ def config2_subset(sys: System, natom: int = 128) -> System:
     return sys.subset_atoms(order[:natom])
 
 
-def config3(seed: int = 3, nsys: int = 64, natom_range=(20, 400)) -> List[System]:
+def uneven_batch(seed: int = 3, nsys: int = 64, natom_range=(20, 400)) -> List[System]:
     """Independent systems of uneven size: atom counts uniform in natom_range,
-    l_max uniform in {1, 2}, shells and P as in config 1 (child seeds)."""
+    l_max uniform in {1, 2}, shells and P as in the 256-atom lattice (child seeds)."""
     ss = np.random.SeedSequence(seed)
     children = ss.spawn(nsys)
     out = []
@@ -235,7 +235,7 @@ def config3(seed: int = 3, nsys: int = 64, natom_range=(20, 400)) -> List[System
         n = int(r.integers(natom_range[0], natom_range[1] + 1))
         lmax = int(r.integers(1, 3))
         sub_seed = int(r.integers(0, 2**31 - 1))
-        out.append(lattice_system(n, sub_seed, lmax=lmax, name=f"config3_sys{i}"))
+        out.append(lattice_system(n, sub_seed, lmax=lmax, name=f"batch_sys{i}"))
     return out
 
 

@@ -45,7 +45,7 @@ def _sys_args(s):
     (lambda s: s.shell_nprim.__setitem__(0, 17), hfx.HFX_EUNSUPPORTED),
 ])
 def test_invalid_basis_rejected_on_host(mutate, status):
-    s = hi.config0()
+    s = hi.sp8_cluster()
     mutate(s)
     with pytest.raises(hfx.HfxError) as e:
         hfx.build_shell_pairs(*_sys_args(s), o=hfx.opts(), stream=0)
@@ -76,7 +76,7 @@ def test_too_many_functions_rejected_on_host():
     (dict(flags=6), hfx.HFX_EINVAL),
 ])
 def test_invalid_options_rejected_on_host(kw, status):
-    s = hi.config0()
+    s = hi.sp8_cluster()
     flags = kw.pop("flags", None)
     o = hfx.opts(**kw)
     if flags is not None:

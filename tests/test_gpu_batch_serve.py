@@ -75,7 +75,7 @@ def test_batch_equals_solo_and_oracle(prec):
 
 
 def test_batch_rejects_duplicate_handle():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     o = hfx.opts(omega=0.11)
     p = hfx.pairs_from_system(s, o)
     P = torch.from_numpy(s.P).cuda()
@@ -136,7 +136,7 @@ def test_served_equals_solo_in_mix():
 
 
 def test_server_admission_and_errors():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     o = hfx.opts(omega=0.11)
     p = hfx.pairs_from_system(s, o)
     P = torch.from_numpy(s.P).cuda()

@@ -46,10 +46,10 @@ def _gpu(s, o, coulomb=False, prim_tau=None):
 
 
 @pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
-@pytest.mark.parametrize("case", ["config0", "dzp8", "dzp6_full"])
+@pytest.mark.parametrize("case", ["sp8_cluster", "dzp8", "dzp6_full"])
 def test_density_K_equals_oracle(case, omega):
-    if case == "config0":
-        s, tau = hi.config0(), 1e-10
+    if case == "sp8_cluster":
+        s, tau = hi.sp8_cluster(), 1e-10
     elif case == "dzp8":
         s, tau = hi.lattice_system(8, seed=23, nprim_range=(1, 3)), 1e-8
     else:  # the workload's 3-6 primitives per shell
@@ -114,7 +114,7 @@ def test_density_tiles_span_many_candidates():
 
 
 def test_unknown_flag_rejected():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     o = hfx.opts()
     o.flags = 6
     with pytest.raises(hfx.HfxError) as e:

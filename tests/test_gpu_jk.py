@@ -40,9 +40,9 @@ def _gpu_JK(s, o):
 
 
 @pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
-def test_JK_config0(omega):
-    s = hi.config0()
-    _say("JK config0 omega", omega)
+def test_JK_sp8_cluster(omega):
+    s = hi.sp8_cluster()
+    _say("JK sp8_cluster omega", omega)
     J, K, K1, st = _gpu_JK(s, hfx.opts(tau=1e-10, omega=omega))
     Jo, Ko, _, cnt = oracle.build_JK(s, tau=1e-10, omega=omega)
     assert np.abs(J - Jo).max() <= 1e-10
@@ -90,7 +90,7 @@ def test_JK_segmented_and_shard_free(monkeypatch):
 
 
 def test_JK_rejects_aliasing():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     o = hfx.opts(omega=0.11)
     p = hfx.pairs_from_system(s, o)
     P = torch.from_numpy(s.P).cuda()
@@ -134,7 +134,7 @@ def test_shards_sum_to_full_build(nshards):
 
 
 def test_JK_leading_dimension():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     n = s.nbf
     big = torch.zeros((n, n + 5), dtype=torch.float64, device="cuda")
     big[:, :n] = torch.from_numpy(s.P).cuda()

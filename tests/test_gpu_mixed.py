@@ -68,7 +68,7 @@ def test_mixed_vs_oracle_dzp(omega):
 
 
 def test_mixed_cut_zero_is_fp64():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     K64, _ = _run(s, hfx.opts(tau=1e-10, omega=0.11))
     Km, st = _run(s, hfx.opts(tau=1e-10, omega=0.11, prec=hfx.PREC_MIXED, mixed_cut=0.0))
     assert st["quartets_fp32"] == 0
@@ -77,17 +77,17 @@ def test_mixed_cut_zero_is_fp64():
 
 def test_all_fp32_error_is_bounded_and_measured():
     """Cut above every bound: every quartet in FP32 -- still FP64 accumulation."""
-    s = hi.config0()
+    s = hi.sp8_cluster()
     Ko, _, cnt = oracle.build_K(s, tau=1e-10, omega=0.11)
     Km, st = _run(s, hfx.opts(tau=1e-10, omega=0.11, prec=hfx.PREC_MIXED, mixed_cut=1e30))
     err = np.abs(Km - Ko).max()
-    _say("all-FP32 config0 max|dK|", err, "max|K|", np.abs(Ko).max())
+    _say("all-FP32 sp8_cluster max|dK|", err, "max|K|", np.abs(Ko).max())
     assert st["quartets_fp32"] == cnt["quartets"]
     assert err <= 1e-5 * np.abs(Ko).max()
 
 
 def test_mixed_vs_fp64_gpu_larger():
-    """24-atom DZP lattice (the config-1 recipe at reduced size): mixed vs the
+    """24-atom DZP lattice (the 256-atom lattice recipe at reduced size): mixed vs the
     FP64 GPU path (itself held to the oracle above)."""
     s = hi.lattice_system(24, seed=2)
     K64, st64 = _run(s, hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE))

@@ -51,7 +51,7 @@ def _spd_small(seed=21, natom=3, nprim=(1, 3)):
 
 @pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
 def test_schwarz_factors(omega):
-    for s in (hi.config0(), _spd_small()):
+    for s in (hi.sp8_cluster(), _spd_small()):
         _say("schwarz", s.meta["name"], omega)
         p = hfx.pairs_from_system(s)
         q = hfx.schwarz_bounds(p, hfx.opts(omega=omega))
@@ -93,11 +93,11 @@ def test_raw_integrals_every_class(omega):
 
 @pytest.mark.parametrize("prim_tau", [0.0, None])
 @pytest.mark.parametrize("omega", [0.0, hi.OMEGA_HSE])
-def test_K_config0(omega, prim_tau):
+def test_K_sp8_cluster(omega, prim_tau):
     """prim_tau = 0: every primitive quartet (same counts as the oracle);
     default: primitive quartets with bound below 1e-6 tau skipped."""
-    s = hi.config0()
-    _say("K config0", omega, prim_tau)
+    s = hi.sp8_cluster()
+    _say("K sp8_cluster", omega, prim_tau)
     Ko, _, cnt = oracle.build_K(s, tau=1e-10, omega=omega)
     Kg, st, _ = _gpu_K(s, 1e-10, omega, stats=True, prim_tau=prim_tau)
     _say("  max |dK|", np.abs(Kg - Ko).max(), "prim quartets", st["prim_quartets"], "of", cnt["prim_quartets"])
@@ -154,14 +154,14 @@ def test_K_degenerate_single_shell_and_s_only():
 
 
 def test_K_everything_screened_is_zero():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     Kg, st, _ = _gpu_K(s, 1e6, 0.0, stats=True)
     assert st["quartets"] == 0
     assert not Kg.any()
 
 
 def test_K_asymmetric_P_rejected():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     p = hfx.pairs_from_system(s)
     P = torch.from_numpy(s.P).cuda()
     P[0, 1] += 1e-3
@@ -172,7 +172,7 @@ def test_K_asymmetric_P_rejected():
 
 
 def test_K_leading_dimension():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     n = s.nbf
     big = torch.zeros((n, n + 7), dtype=torch.float64, device="cuda")
     big[:, :n] = torch.from_numpy(s.P).cuda()
@@ -246,12 +246,12 @@ def test_segmented_launch(monkeypatch, prec):
     assert torch.abs(K2 - K1).max().item() <= 1e-12
 
 
-def test_full_size_config1_sampled():
+def test_full_size_dzp256_lattice_sampled():
     """configs-1 system at full size (1280 shells): all 819,840 Schwarz factors
     on the GPU; a sample of them and of raw quartet integrals (every class)
     against the oracle one by one."""
-    s = hi.config1()
-    _say("config1 pairs")
+    s = hi.dzp256_lattice()
+    _say("dzp256_lattice pairs")
     p = hfx.pairs_from_system(s)
     q = hfx.schwarz_bounds(p, hfx.opts(omega=hi.OMEGA_HSE))
     assert q.shape == (1280 * 1281 // 2,)
@@ -281,7 +281,7 @@ def test_full_size_bench_shard_properties():
     tau = 1e-10): K is linear in P (K(P + 2E) = K(P) + 2 K(E) for a
     symmetric E, so no P-dependent work is skipped and no update is lost or
     doubled between runs), exactly symmetric, and zero for P = 0."""
-    s = hi.config1()
+    s = hi.dzp256_lattice()
     o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
     p = hfx.pairs_from_system(s, o)
     P = torch.from_numpy(s.P).cuda()

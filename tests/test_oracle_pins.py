@@ -380,8 +380,8 @@ def test_eight_fold_symmetry_schwarz_and_digestion(small_spd, omega):
             p += 1
 
 
-def test_config0_K_brute_force_both_operators():
-    s = hi.config0()
+def test_sp8_cluster_K_brute_force_both_operators():
+    s = hi.sp8_cluster()
     for omega in (0.0, hi.OMEGA_HSE):
         G = oracle.eri_tensor(s, omega=omega)
         Kb = np.einsum("ijkl,jl->ik", G, s.P)
@@ -428,8 +428,8 @@ def test_J_single_s_function_closed_form():
         assert abs(K[0, 0] - 0.7 * float(val)) < 1e-15
 
 
-def test_J_config0_brute_force():
-    s = hi.config0()
+def test_J_sp8_cluster_brute_force():
+    s = hi.sp8_cluster()
     G = oracle.eri_tensor(s, omega=hi.OMEGA_HSE)
     J, _, _, cnt = oracle.build_JK(s, tau=0.0, omega=hi.OMEGA_HSE)
     assert np.abs(J - np.einsum("ijkl,kl->ij", G, s.P)).max() < 1e-13
@@ -438,7 +438,7 @@ def test_J_config0_brute_force():
 
 def test_screening_error_bound():
     """K(tau) - K(0) is bounded by the dropped quartets' Schwarz bounds."""
-    s = hi.config0()
+    s = hi.sp8_cluster()
     K0, Q, _ = oracle.build_K(s, tau=0.0, omega=0.11)
     for tau in (1e-6, 1e-4, 1e-2):
         Kt, _, cnt = oracle.build_K(s, tau=tau, omega=0.11)
@@ -511,9 +511,9 @@ def test_si64_basis_counts():
 
 
 def test_config_sizes():
-    c0 = hi.config0()
+    c0 = hi.sp8_cluster()
     assert c0.nshell == 16 and c0.nbf == 32
-    c1 = hi.config1()
+    c1 = hi.dzp256_lattice()
     assert c1.nshell == 1280 and c1.nbf == 3328 and c1.natom == 256
     assert np.allclose(c1.P, c1.P.T)
 
@@ -676,10 +676,10 @@ def test_contracted_high_class_against_mcmurchie_davidson(omega):
 
 def test_digest_list_reproduces_build_K():
     """The list digestion behind the CPU baseline: the screened unique quartets
-    of config0 (p >= q, Q_p Q_q >= tau, by the oracle's own Schwarz factors)
+    of sp8_cluster (p >= q, Q_p Q_q >= tau, by the oracle's own Schwarz factors)
     digested as a list, then K' + K'^T, equal the screened build_K (itself held
     to the brute-force n^4 contraction)."""
-    s = hi.config0()
+    s = hi.sp8_cluster()
     tau = 1e-10
     K, Q, cnt = oracle.build_K(s, tau=tau, omega=0.11)
     qmax = Q.max()
@@ -783,7 +783,7 @@ def test_density_screening_reduces_to_schwarz_for_unit_blocks():
 
 
 def test_density_screening_tau_zero_keeps_everything():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     K0, Q, c0 = oracle.build_K(s, tau=0.0, omega=0.11)
     Kd, _, cd = oracle.build_K_density(s, tau=0.0, omega=0.11)
     assert cd["quartets"] == c0["quartets"] == 136 * 137 // 2

@@ -61,7 +61,7 @@ def test_noalloc_equals_build_K_two_calls(prec):
 
 
 def test_noalloc_refuses_unprepared_handle():
-    s = hi.config0()
+    s = hi.sp8_cluster()
     o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
     p = hfx.pairs_from_system(s, o)
     P = torch.from_numpy(s.P).cuda()
