@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle timing leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
-    ap.add_argument("--mixed-cut", type=float, default=1e-7, help="tuned FP32 cut on Q_IJ Q_KL")
+    ap.add_argument("--mixed-cut", type=float, default=1e-5, help="FP32 cut on the error scale E_IJ E_KL")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-jk", action="store_true", help="skip the Coulomb + exchange leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served leg")

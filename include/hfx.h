@@ -76,9 +76,13 @@ typedef struct {
 
 /* Options.  tau: Schwarz drop tolerance (>= 0; Sec. 3 uses 1e-5, the
  * synthetic workloads 1e-10).  op/omega: kernel; ERFC with omega == 0 is
- * the Coulomb kernel.  prec: FP64, or MIXED, where quartets whose bound
- * Q_IJ Q_KL is below mixed_cut are evaluated in FP32 (FP64 large-T Boys,
- * FP64 bounds and FP64 accumulation into K).  prim_tau (>= 0): inside a
+ * the Coulomb kernel.  prec: FP64, or MIXED, where quartets whose FP32
+ * error scale E_IJ E_KL is below mixed_cut are evaluated in FP32 (FP64
+ * large-T Boys, FP64 bounds, horizontal recurrence and accumulation into K).
+ * E_IJ = s_la s_lb (1 + max_i |AB_i|)^lb sqrt(max_e [e0|e0]) >= Q_IJ (s_l =
+ * 1, 1, 2 for s, p, d) bounds the values the horizontal recurrence takes in,
+ * times the sum of its coefficients: the size of a quartet's FP32 rounding
+ * error relative to FP32 epsilon.  prim_tau (>= 0): inside a
  * computed quartet, primitive quartets whose bound B_ab B_cd is below
  * prim_tau may be skipped, where B_ab is the Schwarz factor of the single
  * primitive pair (a bound on every primitive contribution); 0 keeps every
@@ -233,7 +237,7 @@ hfx_status hfx_submit(hfx_server s, hfx_pairs p, const double *P_dev, double *K_
  * or the status of the failed build. */
 hfx_status hfx_poll(hfx_server s, uint64_t ticket, int32_t *done, hfx_stats *st);
 
-/* Number of spherical functions and shells of a pair handle. */
+/* Number of spherical functions and of shell pairs, n_shell (n_shell + 1) / 2, of a pair handle. */
 int64_t hfx_pairs_nbf(hfx_pairs p);
 int64_t hfx_pairs_npair(hfx_pairs p);
 /* Device bytes held by a pair handle. */

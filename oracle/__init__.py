@@ -14,7 +14,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "_build", "liboracle.so")
+# HFX_ORACLE_SO: load another build of the same source (the sanitizer build
+# of the tests); it is never compiled here.
+_SO = os.environ.get("HFX_ORACLE_SO") or os.path.join(_HERE, "_build", "liboracle.so")
 _lib = None
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -33,10 +35,24 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+def build_sanitized(path: str) -> str:
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every finding fatal) into `path`.  Loading it needs the ASan runtime
+    preloaded into the process (LD_PRELOAD)."""
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    src = os.path.join(_HERE, "hfx_oracle.c")
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                           "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                           "-fno-sanitize-recover=undefined", "-o", path, src, "-lm"])
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO):
+            if os.environ.get("HFX_ORACLE_SO"):
+                raise FileNotFoundError(_SO)
             build(force=True)
         L = ctypes.CDLL(_SO)
         L.oracle_boys.restype = ctypes.c_double

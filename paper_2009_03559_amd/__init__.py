@@ -121,7 +121,7 @@ def _check(rc):
 PRIM_TAU_REL = 1e-6  # default primitive-quartet threshold relative to tau
 
 
-MIXED_CUT = 1e-7  # tuned: 1e-6 gives 1.7e-6 max |dK| on the 256-atom shard, 1e-5 gives ~2e-5
+MIXED_CUT = 1e-5  # FP32 iff E_IJ E_KL < cut: 1.1e-10 max |dK| on the 128-atom subset of the 1024-atom lattice
 
 
 def opts(tau=1e-10, omega=0.0, prec=PREC_FP64, mixed_cut=MIXED_CUT, op=None, prim_tau=None,

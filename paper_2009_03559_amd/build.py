@@ -25,6 +25,16 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-munsafe-fp-ato
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-I" + GEN]
 
 
+# HFX_HOST_SANITIZE=1: AddressSanitizer and UndefinedBehaviorSanitizer on the
+# host code of the runtime (device code unchanged).  The library does not
+# link the sanitizer runtime: the program that loads it provides it (an
+# executable built with the same sanitizers, or a preloaded shared runtime).
+HOST_SANITIZE = os.environ.get("HFX_HOST_SANITIZE") == "1"
+HOST_SOURCES = ("hfx_host.hip", "hfx_serve.hip", "hfx_noalloc.hip")
+SAN_FLAGS = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
 COMMON_HEADERS = [os.path.join(CSRC, "hfx_device.hpp"), os.path.join(CSRC, "hfx_internal.hpp"),
                   os.path.join(ROOT, "include", "hfx.h")]
 
@@ -46,7 +56,8 @@ def _stale(src: str) -> bool:
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    extra = SAN_FLAGS if HOST_SANITIZE and os.path.basename(src) in HOST_SOURCES else []
+    cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-4000:]}")
@@ -62,11 +73,12 @@ def build(jobs: int | None = None, verbose: bool = True, only_changed: bool = Fa
     subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_eri.py"), "--outdir", GEN,
                            "--model", os.path.join(GEN, "model.json")])
     srcs = sorted(os.path.join(GEN, f) for f in os.listdir(GEN) if f.endswith(".hip"))
-    srcs += [os.path.join(CSRC, f) for f in ("hfx_host.hip", "hfx_serve.hip", "hfx_noalloc.hip")]
+    srcs += [os.path.join(CSRC, f) for f in HOST_SOURCES]
     # largest classes first so the pool finishes together (a class's
     # Coulomb-digesting variant shares its header)
     srcs.sort(key=lambda s: -os.path.getsize(_header_of(s)) if os.path.exists(_header_of(s)) else 0)
-    todo = [s for s in srcs if _stale(s)] if only_changed else srcs
+    todo = [s for s in srcs if _stale(s) or (HOST_SANITIZE and os.path.basename(s) in HOST_SOURCES)] \
+        if only_changed else srcs
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
         for o in ex.map(_compile, todo):

@@ -116,6 +116,55 @@ __device__ __forceinline__ void boys(double x, const double *__restrict__ tab, d
     }
 }
 
+// The same F_m(x) in two steps, so that a caller can issue the table loads of
+// several arguments before it waits for any (the erfc kernel evaluates two per
+// primitive quartet).  boys_fetch reads the row nearest x, clamped to the
+// table so that the load stays in bounds for any x; boys_eval takes the
+// Taylor value from that row for every lane, then replaces it by the
+// large-argument form where x >= 36.  For x < 36 the arithmetic is that of
+// boys().
+template <int L>
+__device__ __forceinline__ void boys_fetch(double x, const double *__restrict__ tab, double4 &lo, double4 &hi) {
+    const double xc = fmin(fmax(x, 0.0), BOYS_TMAX);
+    const int i = __double2int_rn(xc * BOYS_INVH);
+    const double *r = tab + ((size_t)L * BOYS_NROW + i) * BOYS_NTAY;
+    lo = *reinterpret_cast<const double4 *>(r);
+    hi = *reinterpret_cast<const double4 *>(r + 4);
+}
+
+template <int L>
+__device__ __forceinline__ void boys_eval(double x, const double4 &lo, const double4 &hi, double *F) {
+    const double xc = fmin(fmax(x, 0.0), BOYS_TMAX);
+    const int i = __double2int_rn(xc * BOYS_INVH);
+    const double u = i * BOYS_H - xc;
+    double f = hi.z;
+    f = fma(f, u, hi.y);
+    f = fma(f, u, hi.x);
+    f = fma(f, u, lo.w);
+    f = fma(f, u, lo.z);
+    f = fma(f, u, lo.y);
+    f = fma(f, u, lo.x);
+    F[L] = f;
+    double e = fma(u, 1.0 / 720.0, 1.0 / 120.0);
+    e = fma(e, u, 1.0 / 24.0);
+    e = fma(e, u, 1.0 / 6.0);
+    e = fma(e, u, 0.5);
+    e = fma(e, u, 1.0);
+    e = fma(e, u, 1.0);
+    const double ex = hi.w * e;
+    const double x2 = 2.0 * xc;
+#pragma unroll
+    for (int m = L - 1; m >= 0; --m) F[m] = fma(x2, F[m + 1], ex) * (1.0 / (2 * m + 1));
+    if (!(x < BOYS_TMAX)) {
+        const double exl = (double)__expf(-(float)x);
+        const double rs = rsqrt(x);
+        F[0] = 0.88622692545275801365 * rs;  // sqrt(pi)/2
+        const double h = 0.5 * rs * rs;       // 1/(2x)
+#pragma unroll
+        for (int m = 0; m < L; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -exl) * h;
+    }
+}
+
 // FP32 Boys: x < 36 from the FP32 table (Taylor to fourth order around the
 // nearest grid point, |u| <= 1/64, truncation below 1e-11 relative) and the
 // downward recursion in FP32; x >= 36 in FP64 (F_0 then upward), rounded.
@@ -196,12 +245,22 @@ __device__ __forceinline__ void prim_quartet_p(const PrimRec &b, double kz, doub
     const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
     const double pref = b.K * kK * rs;
     double g[C::L + 1];
-    boys<C::L>(T, tab, g);
     if (op) {
         const double th = om * rsqrt(om2 + rho);  // theta
         const double th2 = th * th;
         double g2[C::L + 1];
-        boys<C::L>(th2 * T, tab, g2);
+        if constexpr (C::L >= 4) {
+            // both table rows in flight before either is needed: these
+            // classes run one or few waves per SIMD, which exposes waits
+            double4 lo1, hi1, lo2, hi2;
+            boys_fetch<C::L>(T, tab, lo1, hi1);
+            boys_fetch<C::L>(th2 * T, tab, lo2, hi2);
+            boys_eval<C::L>(T, lo1, hi1, g);
+            boys_eval<C::L>(th2 * T, lo2, hi2, g2);
+        } else {
+            boys<C::L>(T, tab, g);
+            boys<C::L>(th2 * T, tab, g2);
+        }
         double f = th * pref;
 #pragma unroll
         for (int m = 0; m <= C::L; ++m) {
@@ -209,6 +268,7 @@ __device__ __forceinline__ void prim_quartet_p(const PrimRec &b, double kz, doub
             f *= th2;
         }
     } else {
+        boys<C::L>(T, tab, g);
 #pragma unroll
         for (int m = 0; m <= C::L; ++m) g[m] *= pref;
     }
