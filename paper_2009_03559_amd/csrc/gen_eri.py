@@ -671,7 +671,7 @@ PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 # more slices recompute more of the shared recurrence.
 DEFAULT_SPLITS = {
     (2, 1, 1, 1): 2, (2, 1, 2, 0): 1, (2, 2, 1, 0): 1, (2, 2, 2, 0): 3,
-    (2, 1, 2, 1): 3, (2, 2, 1, 1): 3, (2, 2, 2, 1): 5, (2, 2, 2, 2): 12,
+    (2, 1, 2, 1): 3, (2, 2, 1, 1): 3, (2, 2, 2, 1): 5, (2, 2, 2, 2): 10,
 }
 
 # Override for tuning: HFX_SPLITS="2221:16,2222:32".
@@ -688,6 +688,15 @@ DEFAULT_SPLITS_F32 = dict(DEFAULT_SPLITS)
 for _kv in filter(None, os.environ.get("HFX_SPLITS_F32", "").split(",")):
     _k, _v = _kv.split(":")
     DEFAULT_SPLITS_F32[tuple(int(c) for c in _k)] = int(_v)
+
+# Waves per workgroup of the FP64 quartet kernel, per class (classes not
+# listed: 1; tuning: HFX_WPB="1000:4").  Four-wave workgroups for the nine
+# lightest classes, which hold about four waves per SIMD where their
+# registers would allow eight, made them 2-28 % slower.
+WPB = {}
+for _kv in filter(None, os.environ.get("HFX_WPB", "").split(",")):
+    _k, _v = _kv.split(":")
+    WPB[tuple(int(c) for c in _k)] = int(_v)
 
 # Minimum waves per SIMD asked of the register allocator, per class (classes
 # not listed: 1).  (ds|ds) gains from two waves; the other mid classes lose.
@@ -706,10 +715,10 @@ def write_jk_tu(outdir, tag, suffix, nm, kernel, launcher, swap="false"):
         f'#include "eri_{tag}{suffix}.h"',
         "namespace hfx {",
         f"void {launcher}_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
-        f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,  // 8 XCDs x chunk",
+        f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 8ll * {nm}::XCH,  // 8 XCDs x chunk",
         "                  [&](const QuartetArgs &a, unsigned grid) {",
-        f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME({kernel}<{nm}, true{', true' if swap == 'true' else ''}>), dim3(grid), dim3(64), 0, s, a);",
-        "                  });",
+        f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME({kernel}<{nm}, true{', true' if swap == 'true' else ''}>), dim3(grid), dim3(64 * {nm}::WPB), 0, s, a);",
+        f"                  }}, {nm}::WPB);",
         "}",
         "}  // namespace hfx",
     ]
@@ -727,19 +736,19 @@ def write_per_tu(outdir, tag, nm, la, lb, lc, ld):
         f'#include "eri_{tag}.h"',
         "namespace hfx {",
         f"void launch_eriper_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
-        f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,",
+        f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 8ll * {nm}::XCH,",
         "                  [&](const QuartetArgs &a, unsigned grid) {",
-        f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri<{nm}, false, false, true>), dim3(grid), dim3(64), 0, s, a);",
-        "                  });",
+        f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri<{nm}, false, false, true>), dim3(grid), dim3(64 * {nm}::WPB), 0, s, a);",
+        f"                  }}, {nm}::WPB);",
         "}",
     ]
     if (la, lb) != (lc, ld):
         lines += [
             f"void launch_eriperS_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
-            f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,",
+            f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 8ll * {nm}::XCH,",
             "                  [&](const QuartetArgs &a, unsigned grid) {",
-            f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri<{nm}, false, true, true>), dim3(grid), dim3(64), 0, s, a);",
-            "                  });",
+            f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri<{nm}, false, true, true>), dim3(grid), dim3(64 * {nm}::WPB), 0, s, a);",
+            f"                  }}, {nm}::WPB);",
             "}",
         ]
     else:
@@ -753,11 +762,13 @@ def write_per_tu(outdir, tag, nm, la, lb, lc, ld):
 # (for these classes the recurrence shared between slices is smaller that way),
 # with the slice counts of the exchanged class.  The digestion images are then
 # the transposes of the usual ones, which K = K' + K'^T absorbs.  FP64 direct
-# and persistent launches.  Measured on the 256-atom shard: (dp|pp) -8 %,
-# (dd|pp) -7 %, (dd|ds) -4 %; (dd|dp) exchanged spills to scratch and stays
-# as it is.
+# and persistent launches.  Measured on the 256-atom shard against the
+# unexchanged class: (dp|pp) -8 %, (dd|pp) -7 %, (dd|ds) -4 %; then, with the
+# slice counts re-measured: (dp|pp) in 1 slice instead of 2 -16 %, (dd|pp) in
+# 2 instead of 3 -12 %, (ds|pp) -9 % and (dd|ps) -6 % exchanged; (dd|dp),
+# (dp|ds) and (dp|ps) exchanged are 2-13 % slower and stay as they are.
 # HFX_TRANSPOSED="2111:2,2211:3" overrides (tuning); "none" turns it off.
-TRANSPOSED = {(2, 1, 1, 1): 2, (2, 2, 1, 1): 3, (2, 2, 2, 0): 2}
+TRANSPOSED = {(2, 1, 1, 1): 1, (2, 2, 1, 1): 2, (2, 2, 2, 0): 2, (2, 2, 1, 0): 1, (2, 0, 1, 1): 1}
 _tr = os.environ.get("HFX_TRANSPOSED", "")
 if _tr == "none":
     TRANSPOSED = {}
@@ -800,6 +811,11 @@ def emit_struct(em, la, lb, lc, ld, nm, G):
     G = min(G, NF)  # no empty slices
     em.lines.append(f"  static constexpr int NSPLIT = {G};")
     em.lines.append(f"  static constexpr int WAVES = {WAVES.get((la, lb, lc, ld), 1)};")
+    # waves (independent logical blocks) per workgroup of the FP64 quartet
+    # kernel, and the XCD chunk in workgroups (8 tiles' slices)
+    wpb = WPB.get((la, lb, lc, ld), WPB.get((lc, ld, la, lb), 1)) if em.T == "double" else 1
+    em.lines.append(f"  static constexpr int WPB = {wpb};")
+    em.lines.append(f"  static constexpr int XCH = {(8 * G + wpb - 1) // wpb};")
     split_cost = []
     groups = best_split(la, lb, lc, ld, G) if G > 1 else [[f for d in range(lc, F + 1) for f in cart(d)]]
     nacc_p = []
@@ -913,10 +929,14 @@ def generate(outdir, T="double", splits=None):
         if T == "double" and (la, lb, lc, ld) in TRANSPOSED:
             # the same integrals with the pairs' roles exchanged, sliced over
             # the components of the original bra pair (see TRANSPOSED)
-            emit_struct(em, lc, ld, la, lb, nm + "T", TRANSPOSED[(la, lb, lc, ld)])
+            tinfo = emit_struct(em, lc, ld, la, lb, nm + "T", TRANSPOSED[(la, lb, lc, ld)])
+        else:
+            tinfo = None
         write_if_changed(os.path.join(outdir, f"eri_{tag}{suffix}.h"), "\n".join(em.lines) + "\n")
         model[tag] = dict(vrr_flops=vflops, post_flops=pflops, nacc=NE * NF,
                           nout=nsph, split=G, split_vrr_flops=split_cost)
+        if tinfo is not None:  # the kernel that runs: the exchanged struct
+            model[tag].update(split_exchanged=tinfo[5], split_vrr_flops_exchanged=tinfo[6])
         diag = (la, lb) == (lc, ld)
         if T != "double":
             tu = [
@@ -949,10 +969,10 @@ def generate(outdir, T="double", splits=None):
             f'#include "eri_{tag}{suffix}.h"',
             "namespace hfx {",
             f"void launch_eri_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
-            f"  launch_segments(a0, (long long)nblk * {dn}::NSPLIT, 64ll * {dn}::NSPLIT,  // 8 XCDs x chunk",
+            f"  launch_segments(a0, (long long)nblk * {dn}::NSPLIT, 8ll * {dn}::XCH,  // 8 XCDs x chunk",
             "                  [&](const QuartetArgs &a, unsigned grid) {",
-            f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri<{dn}, false, {sw}>), dim3(grid), dim3(64), 0, s, a);",
-            "                  });",
+            f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri<{dn}, false, {sw}>), dim3(grid), dim3(64 * {dn}::WPB), 0, s, a);",
+            f"                  }}, {dn}::WPB);",
             "}",
             f"void launch_persist_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
             "                        unsigned grid, hipStream_t s) {",

@@ -64,6 +64,7 @@ __device__ __forceinline__ PrimRec32 load_rec(CPrimRec32 *r) {
     return x;
 }
 
+constexpr int MAX_WPB = 4;              // most waves per workgroup of a quartet kernel
 constexpr int BOYS_NROW = 1153;         // grid points 0 .. 36 step 1/32
 constexpr double BOYS_H = 1.0 / 32.0;
 constexpr double BOYS_INVH = 32.0;
@@ -385,16 +386,28 @@ __device__ __forceinline__ int xcd_block(int nblk, int chunk) {
 // segments of whole XCD spans; each segment carries its first logical block.
 long long max_blocks_per_launch();
 
+// wpb: logical blocks (waves) per workgroup; span and the grid count
+// workgroups.
 template <class Launch>
-inline void launch_segments(QuartetArgs a, long long total, long long span, Launch launch) {
-    const long long cap = max_blocks_per_launch() / span * span;
-    const long long seg = cap > span ? cap : span;
+inline void launch_segments(QuartetArgs a, long long total, long long span, Launch launch, int wpb = 1) {
+    const long long capg = max_blocks_per_launch() / wpb / span * span;
+    const long long seg = (capg > span ? capg : span) * wpb;
     for (long long base = 0; base < total; base += seg) {
         const long long n = total - base < seg ? total - base : seg;
         a.blk_base = base;
         a.nblk = (int32_t)n;
-        launch(a, (unsigned)((n + span - 1) / span * span));
+        const long long groups = (n + wpb - 1) / wpb;
+        launch(a, (unsigned)((groups + span - 1) / span * span));
     }
+}
+
+// LDS of one wave becomes visible to the other lanes of the same wave: the
+// wave's LDS operations complete in order, so only the compiler must keep
+// them on their side of this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // First slot q in [l, h) with !(Qp Q[q] >= t); Q is sorted descending.
@@ -446,12 +459,14 @@ __device__ __forceinline__ double dens_weight(const QuartetArgs &a, int bA, int 
 template <class Body>
 __device__ __forceinline__ void ket_tiles(const QuartetArgs &a, int p, const PairHdr &bh, int lo, int cut,
                                           Body body) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     if (!a.dens) {
         for (int q0 = lo; q0 < cut; q0 += 64) body(q0 + lane < cut ? q0 + lane : -1);
         return;
     }
-    __shared__ int queue[128];
+    // one queue per wave: the waves of a workgroup are independent blocks
+    __shared__ int queues[MAX_WPB][128];
+    int *queue = queues[threadIdx.x >> 6];
     const double Qp = a.bra_Q[p];
     int nq = 0;
     for (int c0 = lo; c0 < cut; c0 += 64) {
@@ -464,14 +479,14 @@ __device__ __forceinline__ void ket_tiles(const QuartetArgs &a, int p, const Pai
         const unsigned long long m = __ballot(ok);
         if (ok) queue[nq + __popcll(m & ((1ull << lane) - 1ull))] = q;
         nq += __popcll(m);
-        __syncthreads();
+        wave_sync();
         if (nq >= 64) {
             const int qq = queue[lane];
             const int rest = lane + 64 < nq ? queue[lane + 64] : 0;
-            __syncthreads();
+            wave_sync();
             if (lane + 64 < nq) queue[lane] = rest;
             nq -= 64;
-            __syncthreads();
+            wave_sync();
             body(qq);
         }
     }
@@ -489,7 +504,7 @@ template <class C, int W, int VRRW, bool WJ, bool SWAP, bool PER>
 __device__ __forceinline__ void tile_part(const QuartetArgs &a, int p, int g, int lo, int cut) {
     const PairHdr bh = a.hdr[a.bra_ids[p]];
     const int nkp = a.ket_gnp[g];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const double eps = a.prim_tau;
     // the bra pair is the same for the whole wave: make that explicit so its
     // records are read with scalar loads
@@ -574,10 +589,16 @@ __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p
 // WJ: also digest the Coulomb matrix J from the same quartet values.
 // SWAP: C is the exchanged class (see tile_part).
 // PER: periodic build (see QuartetArgs::nhome).
+// C::WPB waves per workgroup, each an independent logical block (light
+// classes: more than one wave per workgroup lifts the per-CU workgroup limit
+// off their occupancy); the XCD chunks count workgroups.
 template <class C, bool WJ = false, bool SWAP = false, bool PER = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri(QuartetArgs a) {
-    const int lb0 = xcd_block(a.nblk, 8 * C::NSPLIT);
-    if (lb0 < 0) return;
+__global__ __launch_bounds__(64 * C::WPB) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri(QuartetArgs a) {
+    const int ng = (a.nblk + C::WPB - 1) / C::WPB;
+    const int lg = xcd_block(ng, C::XCH);
+    if (lg < 0) return;
+    const int lb0 = lg * C::WPB + (C::WPB > 1 ? (int)(threadIdx.x >> 6) : 0);
+    if (lb0 >= a.nblk) return;
     const long long lb = a.blk_base + lb0;
     const int w = (int)(lb % C::NSPLIT);
     long long t = lb / C::NSPLIT;
@@ -601,7 +622,7 @@ template <class C, int W, bool WJ>
 __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, int lo, int cut) {
     const PairHdr bh = a.hdr[a.bra_ids[p]];
     const int nkp = a.ket_gnp[g];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const float eps = (float)a.prim_tau;
     const int boff = __builtin_amdgcn_readfirstlane(bh.off);
     const int bn = __builtin_amdgcn_readfirstlane(bh.n);
