@@ -589,9 +589,9 @@ __device__ __forceinline__ void tile_dispatch(const QuartetArgs &a, int w, int p
 // WJ: also digest the Coulomb matrix J from the same quartet values.
 // SWAP: C is the exchanged class (see tile_part).
 // PER: periodic build (see QuartetArgs::nhome).
-// C::WPB waves per workgroup, each an independent logical block (light
-// classes: more than one wave per workgroup lifts the per-CU workgroup limit
-// off their occupancy); the XCD chunks count workgroups.
+// C::WPB waves per workgroup, each an independent logical block (a tuning
+// option, one by default: four-wave workgroups made the light classes
+// slower); the XCD chunks count workgroups.
 template <class C, bool WJ = false, bool SWAP = false, bool PER = false>
 __global__ __launch_bounds__(64 * C::WPB) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri(QuartetArgs a) {
     const int ng = (a.nblk + C::WPB - 1) / C::WPB;

@@ -320,7 +320,10 @@ hfx_status batch_impl(int32_t nsys, const hfx_pairs *p, const double *const *P, 
     // autotune the classes not yet known for this device (into scratch K)
     const std::string dn = dev_name();
     std::vector<Tune> tune(2 * HFX_NCLASS);
-    {
+    // HFX_TUNE=0: the default parameters for every class, nothing timed
+    const char *tenv = std::getenv("HFX_TUNE");
+    const bool no_tune = tenv && std::strcmp(tenv, "0") == 0;
+    if (!no_tune) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune();
         bool changed = false;

@@ -74,6 +74,28 @@ def test_batch_equals_solo_and_oracle(prec):
     assert st2["quartets"] == nq
 
 
+def test_batch_default_parameters_equal_tuned():
+    """HFX_TUNE=0 runs the batch with the default launch parameters (no
+    autotuning): the same K and quartet count as the tuned batch."""
+    systems = _systems(n=4, seed=60)
+    o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
+    pairs = [hfx.pairs_from_system(s, o) for s in systems]
+    Ps = [torch.from_numpy(s.P).cuda() for s in systems]
+    K1 = [torch.empty_like(P) for P in Ps]
+    K2 = [torch.empty_like(P) for P in Ps]
+    st1 = hfx.build_K_batch(pairs, Ps, K1, o, stats=True)
+    os.environ["HFX_TUNE"] = "0"
+    try:
+        st2 = hfx.build_K_batch(pairs, Ps, K2, o, stats=True)
+    finally:
+        del os.environ["HFX_TUNE"]
+    torch.cuda.synchronize()
+    _say("batch tuned vs default parameters: quartets", st1["quartets"], st2["quartets"])
+    assert st1["quartets"] == st2["quartets"]
+    for a, b in zip(K1, K2):
+        assert torch.abs(a - b).max().item() <= 1e-12
+
+
 def test_batch_rejects_duplicate_handle():
     s = hi.sp8_cluster()
     o = hfx.opts(omega=0.11)
