@@ -926,7 +926,7 @@ def generate(outdir, T="double", splits=None):
         nm = f"Eri{tag}{suffix}"
         vflops, pflops, NE, NF, nsph, G, split_cost = emit_struct(
             em, la, lb, lc, ld, nm, splits.get((la, lb, lc, ld), 1))
-        if T == "double" and (la, lb, lc, ld) in TRANSPOSED:
+        if (la, lb, lc, ld) in TRANSPOSED:
             # the same integrals with the pairs' roles exchanged, sliced over
             # the components of the original bra pair (see TRANSPOSED)
             tinfo = emit_struct(em, lc, ld, la, lb, nm + "T", TRANSPOSED[(la, lb, lc, ld)])
@@ -938,6 +938,9 @@ def generate(outdir, T="double", splits=None):
         if tinfo is not None:  # the kernel that runs: the exchanged struct
             model[tag].update(split_exchanged=tinfo[5], split_vrr_flops_exchanged=tinfo[6])
         diag = (la, lb) == (lc, ld)
+        # launches of a class in TRANSPOSED use the exchanged struct
+        tr = (la, lb, lc, ld) in TRANSPOSED
+        dn, sw = (nm + "T", "true") if tr else (nm, "false")
         if T != "double":
             tu = [
                 "// Generated by gen_eri.py; do not edit.",
@@ -945,24 +948,21 @@ def generate(outdir, T="double", splits=None):
                 f'#include "eri_{tag}{suffix}.h"',
                 "namespace hfx {",
                 f"void launch_eri32_{tag}(const QuartetArgs &a0, unsigned nblk, hipStream_t s) {{",
-                f"  launch_segments(a0, (long long)nblk * {nm}::NSPLIT, 64ll * {nm}::NSPLIT,  // 8 XCDs x chunk",
+                f"  launch_segments(a0, (long long)nblk * {dn}::NSPLIT, 64ll * {dn}::NSPLIT,  // 8 XCDs x chunk",
                 "                  [&](const QuartetArgs &a, unsigned grid) {",
-                f"                    hipLaunchKernelGGL(k_eri32<{nm}>, dim3(grid), dim3(64), 0, s, a);",
+                f"                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri32<{dn}, false, {sw}>), dim3(grid), dim3(64), 0, s, a);",
                 "                  });",
                 "}",
                 f"void launch_persist32_{tag}(const BatchJob *j, int nj, long long vt, unsigned long long *h, int claim,",
                 "                          unsigned grid, hipStream_t s) {",
-                f"  hipLaunchKernelGGL(k_eri32_persist<{nm}>, dim3(grid), dim3(64), 0, s, j, nj, vt, h, claim);",
+                f"  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eri32_persist<{dn}, {sw}>), dim3(grid), dim3(64), 0, s, j, nj, vt, h, claim);",
                 "}",
-                f"int nsplit32_{tag}() {{ return {nm}::NSPLIT; }}",
+                f"int nsplit32_{tag}() {{ return {dn}::NSPLIT; }}",
             ]
             tu.append("}  // namespace hfx")
             write_if_changed(os.path.join(outdir, f"tu_{tag}{suffix}.hip"), "\n".join(tu) + "\n")
-            write_jk_tu(outdir, tag, suffix, nm, "k_eri32", "launch_erijk32")
+            write_jk_tu(outdir, tag, suffix, dn, "k_eri32", "launch_erijk32", sw)
             continue
-        # direct launches of a class in TRANSPOSED use the exchanged struct
-        tr = (la, lb, lc, ld) in TRANSPOSED
-        dn, sw = (nm + "T", "true") if tr else (nm, "false")
         tu = [
             "// Generated by gen_eri.py; do not edit.",
             '#include "hfx_device.hpp"',

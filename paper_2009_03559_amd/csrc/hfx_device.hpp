@@ -617,8 +617,8 @@ __global__ __launch_bounds__(64 * C::WPB) __attribute__((amdgpu_waves_per_eu(C::
 }
 
 // FP32 counterpart of tile_part: FP32 records, recurrences and contraction,
-// FP64 digestion into K.
-template <class C, int W, bool WJ>
+// FP64 digestion into K.  SWAP as in tile_part.
+template <class C, int W, bool WJ, bool SWAP>
 __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, int lo, int cut) {
     const PairHdr bh = a.hdr[a.bra_ids[p]];
     const int nkp = a.ket_gnp[g];
@@ -647,7 +647,10 @@ __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, 
                 const PrimRec32 b = load_rec(brec + bp);
                 if (!__any(kb * b.B >= eps)) break;
                 nprim += act;
-                prim_quartet32<C, W>(b, k, a.op, om, om2, a.boys32, acc);
+                if constexpr (SWAP)
+                    prim_quartet32<C, W>(k, b, a.op, om, om2, a.boys32, acc);
+                else
+                    prim_quartet32<C, W>(b, k, a.op, om, om2, a.boys32, acc);
             }
         }
         if (act) {
@@ -656,11 +659,12 @@ __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, 
             if (kh.diag) deg *= 0.5;
             if (bh.id == kh.id) deg *= 0.5;
             // horizontal recurrence, spherical transform and digestion in FP64
-            C::template dig<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB, kh.bfA,
-                               kh.bfB, deg, a.P, a.K, a.ld);
+            const PairHdr &x = SWAP ? kh : bh, &y = SWAP ? bh : kh;
+            C::template dig<W>(acc, x.ABx, x.ABy, x.ABz, y.ABx, y.ABy, y.ABz, x.bfA, x.bfB, y.bfA, y.bfB, deg,
+                               a.P, a.K, a.ld);
             if constexpr (WJ)
-                C::template digJ<W>(acc, bh.ABx, bh.ABy, bh.ABz, kh.ABx, kh.ABy, kh.ABz, bh.bfA, bh.bfB, kh.bfA,
-                                    kh.bfB, deg, a.P, a.J, a.ld);
+                C::template digJ<W>(acc, x.ABx, x.ABy, x.ABz, y.ABx, y.ABy, y.ABz, x.bfA, x.bfB, y.bfA,
+                                    y.bfB, deg, a.P, a.J, a.ld);
         }
     });
     if (W == 0 && a.count) {
@@ -669,17 +673,18 @@ __device__ __forceinline__ void tile_part32(const QuartetArgs &a, int p, int g, 
     }
 }
 
-template <class C, int W, bool WJ = false>
+template <class C, int W, bool WJ = false, bool SWAP = false>
 __device__ __forceinline__ void tile_dispatch32(const QuartetArgs &a, int w, int p, int g, int lo, int cut) {
     if (w == W) {
-        tile_part32<C, W, WJ>(a, p, g, lo, cut);
+        tile_part32<C, W, WJ, SWAP>(a, p, g, lo, cut);
     } else if constexpr (W + 1 < C::NSPLIT) {
-        tile_dispatch32<C, W + 1, WJ>(a, w, p, g, lo, cut);
+        tile_dispatch32<C, W + 1, WJ, SWAP>(a, w, p, g, lo, cut);
     }
 }
 
 // WJ: also digest the Coulomb matrix J from the same quartet values.
-template <class C, bool WJ = false>
+// SWAP: C is the exchanged class (see tile_part).
+template <class C, bool WJ = false, bool SWAP = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri32(QuartetArgs a) {
     const int lb0 = xcd_block(a.nblk, 8 * C::NSPLIT);
     if (lb0 < 0) return;
@@ -697,7 +702,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     const int lo2 = lo + sub * a.tq;
     const int cut2 = min(cut, lo2 + a.tq);
     if (cut2 <= lo2) return;
-    tile_dispatch32<C, 0, WJ>(a, w, p, g, lo2, cut2);
+    tile_dispatch32<C, 0, WJ, SWAP>(a, w, p, g, lo2, cut2);
 }
 
 // ----------------------------------------------------------------------
@@ -743,7 +748,7 @@ __device__ __forceinline__ void persist_loop(const BatchJob *__restrict__ jobs, 
             const int lo2 = lo + sub * J.tq;
             const int cut2 = min(cut, lo2 + J.tq);
             if (cut2 <= lo2) continue;
-            if constexpr (F32) tile_dispatch32<C, 0>(J.a, w, p, g, lo2, cut2);
+            if constexpr (F32) tile_dispatch32<C, 0, false, SWAP>(J.a, w, p, g, lo2, cut2);
             else tile_dispatch<C, 0, false, SWAP>(J.a, w, p, g, lo2, cut2);
         }
     }
@@ -755,10 +760,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) 
     persist_loop<C, false, SWAP>(jobs, njobs, vtotal, head, claim);
 }
 
-template <class C>
+template <class C, bool SWAP = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::WAVES))) void k_eri32_persist(
     const BatchJob *__restrict__ jobs, int njobs, long long vtotal, unsigned long long *head, int claim) {
-    persist_loop<C, true>(jobs, njobs, vtotal, head, claim);
+    persist_loop<C, true, SWAP>(jobs, njobs, vtotal, head, claim);
 }
 
 // Slice W's share of the diagonal values (ab|ab) of pair h, then the next
