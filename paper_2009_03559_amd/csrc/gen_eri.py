@@ -810,7 +810,8 @@ def emit_struct(em, la, lb, lc, ld, nm, G):
     _, vflops = emit_vrr(em, la, lb, lc, ld, "vrr")
     G = min(G, NF)  # no empty slices
     em.lines.append(f"  static constexpr int NSPLIT = {G};")
-    em.lines.append(f"  static constexpr int WAVES = {WAVES.get((la, lb, lc, ld), 1)};")
+    # keyed by the class as listed, so an exchanged struct takes its class's value
+    em.lines.append(f"  static constexpr int WAVES = {WAVES.get((la, lb, lc, ld), WAVES.get((lc, ld, la, lb), 1))};")
     # waves (independent logical blocks) per workgroup of the FP64 quartet
     # kernel, and the XCD chunk in workgroups (8 tiles' slices)
     wpb = WPB.get((la, lb, lc, ld), WPB.get((lc, ld, la, lb), 1)) if em.T == "double" else 1
