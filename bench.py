@@ -142,11 +142,13 @@ def batch_leg(a, hfx, hi, torch):
             hfx.build_K_batch(pairs, Ps, Ks, o)
             torch.cuda.synchronize()
             t_default = time.perf_counter() - t0
+            print(f"# batch {name}: default parameters {t_default:.3f} s", file=sys.stderr, flush=True)
         del os.environ["HFX_TUNE"]
         t0 = time.perf_counter()
         hfx.build_K_batch(pairs, Ps, Ks, o)  # first tuned call: autotuning
         torch.cuda.synchronize()
         t_first = time.perf_counter() - t0
+        print(f"# batch {name}: first tuned call {t_first:.3f} s", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         st = hfx.build_K_batch(pairs, Ps, Ks, o, stats=True)
         torch.cuda.synchronize()
@@ -154,8 +156,11 @@ def batch_leg(a, hfx, hi, torch):
         Kb = [K.cpu().numpy() for K in Ks]
         # the same systems one call at a time (lists already resident)
         t0 = time.perf_counter()
-        for p, P, K in zip(pairs, Ps, Ks):
+        for i, (p, P, K) in enumerate(zip(pairs, Ps, Ks)):
             hfx.build_K(p, P, K, o)
+            if i % 16 == 15:
+                torch.cuda.synchronize()
+                print(f"# batch {name}: {i + 1} systems one by one", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
         dmax = max(float(np.abs(K.cpu().numpy() - k).max()) for K, k in zip(Ks, Kb))
