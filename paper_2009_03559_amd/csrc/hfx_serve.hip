@@ -429,10 +429,77 @@ hfx_status batch_impl(int32_t nsys, const hfx_pairs *p, const double *const *P, 
 
 using namespace hfx;
 
+namespace {
+// Systems with at least this many basis functions fill the device on their
+// own and run on the direct kernels; the rest share the persistent launches.
+// Measured on 64 lattice systems: 6-20 atoms (78-260 functions) batched
+// 1.5x faster than one by one, 20-40 atoms (260-520) 0.87x.
+int64_t direct_nbf() {
+    if (const char *e = std::getenv("HFX_BATCH_DIRECT_NBF")) return std::atoll(e);
+    return 300;
+}
+
+void add_stats(hfx_stats &a, const hfx_stats &b) {
+    a.device_s += b.device_s;
+    a.quartets += b.quartets;
+    a.quartets_fp32 += b.quartets_fp32;
+    a.prim_quartets += b.prim_quartets;
+    a.flops += b.flops;
+    for (int c = 0; c < HFX_NCLASS; ++c) {
+        a.class_quartets[c] += b.class_quartets[c];
+        a.class_device_s[c] += b.class_device_s[c];
+        a.class_flops[c] += b.class_flops[c];
+    }
+}
+}  // namespace
+
 extern "C" hfx_status hfx_build_K_batch(int32_t nsys, const hfx_pairs *p, const double *const *P,
                                         double *const *K, const int64_t *ld, const hfx_opts *o, void *stream,
                                         hfx_stats *st) {
-    return batch_impl(nsys, p, P, K, ld, o, stream, st);
+    const auto t0 = std::chrono::steady_clock::now();
+    if (nsys < 0 || (nsys > 0 && (!p || !P || !K || !ld))) return fail(HFX_EINVAL, "bad batch arrays");
+    for (int i = 0; i < nsys; ++i) {
+        if (!p[i] || !P[i] || !K[i]) return fail(HFX_EINVAL, "NULL entry in batch");
+        for (int j = 0; j < i; ++j)
+            if (p[j] == p[i]) return fail(HFX_EINVAL, "a pair handle appears twice in one batch");
+    }
+    const int64_t thr = direct_nbf();
+    std::vector<hfx_pairs> sp;
+    std::vector<const double *> sP;
+    std::vector<double *> sK;
+    std::vector<int64_t> sld;
+    std::vector<int> big;
+    for (int i = 0; i < nsys; ++i) {
+        if (thr > 0 && p[i]->nbf >= thr) {
+            big.push_back(i);
+        } else {
+            sp.push_back(p[i]);
+            sP.push_back(P[i]);
+            sK.push_back(K[i]);
+            sld.push_back(ld[i]);
+        }
+    }
+    if (big.empty()) return batch_impl(nsys, p, P, K, ld, o, stream, st);
+    hfx_stats acc;
+    std::memset(&acc, 0, sizeof(acc));
+    if (!sp.empty()) {
+        hfx_stats s1;
+        const hfx_status s = batch_impl((int32_t)sp.size(), sp.data(), sP.data(), sK.data(), sld.data(), o, stream,
+                                        st ? &s1 : nullptr);
+        if (s != HFX_OK) return s;
+        if (st) add_stats(acc, s1);
+    }
+    for (int i : big) {
+        hfx_stats s1;
+        const hfx_status s = build_K_impl(p[i], P[i], K[i], ld[i], o, 0, 1, stream, st ? &s1 : nullptr);
+        if (s != HFX_OK) return s;
+        if (st) add_stats(acc, s1);
+    }
+    if (st) {
+        acc.latency_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *st = acc;
+    }
+    return HFX_OK;
 }
 
 // -------------------------------------------------------------- server ----

@@ -96,6 +96,27 @@ def test_batch_default_parameters_equal_tuned():
         assert torch.abs(a - b).max().item() <= 1e-12
 
 
+def test_batch_runs_large_systems_on_the_direct_kernels():
+    """A system of at least 300 basis functions is built with the direct
+    kernels inside the batch, the small ones through the persistent queue:
+    every K equals its solo build, and the counts add up."""
+    systems = _systems(n=3, seed=70) + [hi.lattice_system(24, seed=71, nprim_range=(1, 2))]
+    assert systems[-1].nbf >= 300 and all(s.nbf < 300 for s in systems[:-1])
+    o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
+    pairs = [hfx.pairs_from_system(s, o) for s in systems]
+    Ps = [torch.from_numpy(s.P).cuda() for s in systems]
+    Ks = [torch.empty_like(P) for P in Ps]
+    st = hfx.build_K_batch(pairs, Ps, Ks, o, stats=True)
+    torch.cuda.synchronize()
+    nq = 0
+    for s, K in zip(systems, Ks):
+        Ksolo, sts = _solo(s, o)
+        assert np.abs(K.cpu().numpy() - Ksolo).max() <= 1e-12
+        nq += sts["quartets"]
+    _say("batch with one direct system: quartets", st["quartets"], nq)
+    assert st["quartets"] == nq
+
+
 def test_batch_rejects_duplicate_handle():
     s = hi.sp8_cluster()
     o = hfx.opts(omega=0.11)
