@@ -209,7 +209,7 @@ hfx_status hfx_build_K_periodic(hfx_pairs p, int32_t nhome_shell, const double *
 /* Many independent systems in one persistent launch per pass, fed by a
  * device work queue (Sec. 5 proposes dynamic distribution of the quartet
  * work; here the queue is shared by all systems).  A system with at least
- * 300 basis functions (environment HFX_BATCH_DIRECT_NBF; 0 = never) fills
+ * 250 basis functions (environment HFX_BATCH_DIRECT_NBF; 0 = never) fills
  * the device on its own and is built with the kernels of hfx_build_K
  * instead, one after another on the same stream.  Arrays of length nsys;
  * every system follows the rules of hfx_build_K.  st (optional) sums over

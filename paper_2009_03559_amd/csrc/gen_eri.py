@@ -667,8 +667,10 @@ PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 
 # Number of ket slices (waves) per quartet for the classes whose contracted
 # array does not fit one lane's registers.  Measured on the 256-atom DZP
-# shard: fewer slices than these spill registers to scratch (2-3x slower),
-# more slices recompute more of the shared recurrence.
+# shard: more slices recompute more of the shared recurrence; fewer spill
+# registers to scratch, mostly 2-3x slower, though (dd|dd) in 10 slices
+# (2.7 KB of scratch per lane) runs 10 % faster than in 12 and 3 % faster
+# than in 9.
 DEFAULT_SPLITS = {
     (2, 1, 1, 1): 2, (2, 1, 2, 0): 1, (2, 2, 1, 0): 1, (2, 2, 2, 0): 3,
     (2, 1, 2, 1): 3, (2, 2, 1, 1): 3, (2, 2, 2, 1): 5, (2, 2, 2, 2): 10,

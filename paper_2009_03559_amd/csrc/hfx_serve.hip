@@ -432,11 +432,13 @@ using namespace hfx;
 namespace {
 // Systems with at least this many basis functions fill the device on their
 // own and run on the direct kernels; the rest share the persistent launches.
-// Measured on 64 lattice systems: 6-20 atoms (78-260 functions) batched
-// 1.5x faster than one by one, 20-40 atoms (260-520) 0.87x.
+// Measured on 64 lattice systems, batch time against one by one: all in the
+// queue, 6-20 atoms (78-260 functions) 1.5x faster, 20-40 atoms (260-520)
+// 0.87x; from 300 functions direct 1.55x / 0.93x, from 200 1.38x / 0.99x,
+// from 150 1.19x / 1.00x.
 int64_t direct_nbf() {
     if (const char *e = std::getenv("HFX_BATCH_DIRECT_NBF")) return std::atoll(e);
-    return 300;
+    return 250;
 }
 
 void add_stats(hfx_stats &a, const hfx_stats &b) {

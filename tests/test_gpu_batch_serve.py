@@ -97,11 +97,11 @@ def test_batch_default_parameters_equal_tuned():
 
 
 def test_batch_runs_large_systems_on_the_direct_kernels():
-    """A system of at least 300 basis functions is built with the direct
+    """A system of at least 250 basis functions is built with the direct
     kernels inside the batch, the small ones through the persistent queue:
     every K equals its solo build, and the counts add up."""
     systems = _systems(n=3, seed=70) + [hi.lattice_system(24, seed=71, nprim_range=(1, 2))]
-    assert systems[-1].nbf >= 300 and all(s.nbf < 300 for s in systems[:-1])
+    assert systems[-1].nbf >= 250 and all(s.nbf < 250 for s in systems[:-1])
     o = hfx.opts(tau=1e-10, omega=hi.OMEGA_HSE)
     pairs = [hfx.pairs_from_system(s, o) for s in systems]
     Ps = [torch.from_numpy(s.P).cuda() for s in systems]
